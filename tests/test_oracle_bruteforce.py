@@ -1,0 +1,213 @@
+"""Brute-force, invariant and comparator checks of the FP64 oracle.
+
+The compositing walk of the oracle (front-to-back, skip below 1/255, stop
+before T drops under 1e-4) is checked against the explicit product form
+C(p) = sum_{i<=k} c_i a_i prod_{j<i} (1 - a_j) evaluated in mpmath over the
+(z, index)-ordered candidates, on tiny scenes; then invariants that hold for
+any scene (transmittance range, weight sum, colour bound, depth range,
+permutation, rigid-motion invariance).
+"""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+import oracle
+import scenegen
+
+mp.mp.dps = 40
+F32 = lambda x: float(np.float32(x))  # noqa: E731
+AMAX, AMIN, TMIN = F32(0.99), F32(1 / 255), F32(1e-4)
+IDENT_POSE = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1).astype(np.float32)
+TINY_INTR = [8.0, 8.0, 4.0, 4.0]
+
+
+def product_form(rec, W, H):
+    """Explicit product formula per pixel from the per-Gaussian records."""
+    n = len(rec["u"])
+    out = np.zeros((H, W, 5))
+    for j in range(H):
+        for i in range(W):
+            cands = []
+            for g in range(n):
+                if not rec["in_front"][g]:
+                    continue
+                dx = mp.mpf(i) + mp.mpf(0.5) - mp.mpf(rec["u"][g])
+                dy = mp.mpf(j) + mp.mpf(0.5) - mp.mpf(rec["v"][g])
+                q = (mp.mpf(rec["conic_a"][g]) * dx * dx + 2 * mp.mpf(rec["conic_b"][g]) * dx * dy +
+                     mp.mpf(rec["conic_c"][g]) * dy * dy)
+                a = min(mp.mpf(AMAX), mp.mpf(rec["opacity"][g]) * mp.exp(-q / 2))
+                if a >= AMIN:
+                    cands.append((rec["z"][g], g, a))
+            cands.sort(key=lambda t: (t[0], t[1]))
+            # included prefix: largest k with prod_{j<=k}(1 - a_j) >= T_MIN
+            k, prod = 0, mp.mpf(1)
+            while k < len(cands) and prod * (1 - cands[k][2]) >= TMIN:
+                prod *= 1 - cands[k][2]
+                k += 1
+            rgbz = [mp.mpf(0)] * 5
+            for idx in range(k):
+                z, g, a = cands[idx]
+                w = a
+                for jj in range(idx):
+                    w *= 1 - cands[jj][2]
+                for ch, key in enumerate(("r", "g", "b")):
+                    rgbz[ch] += w * mp.mpf(rec[key][g])
+                rgbz[3] += w * mp.mpf(z)
+                rgbz[4] += w
+            out[j, i, :3] = [float(x) for x in rgbz[:3]]
+            out[j, i, 3] = float(rgbz[3] / rgbz[4]) if rgbz[4] > 0 else 0.0
+            out[j, i, 4] = float(rgbz[4])
+    return out
+
+
+@pytest.mark.parametrize("seed,n,opac_boost", [(0, 6, 0.0), (1, 8, 0.0), (2, 10, 3.0),
+                                                (3, 12, 5.0), (4, 5, -1.0)])
+def test_bruteforce_product_form(seed, n, opac_boost):
+    if opac_boost >= 3.0:   # dense, nearly opaque cluster: the stop rule fires
+        sc = scenegen.tiny_scene(n, seed, sh_degree=(seed % 2) * 3, spread=0.2,
+                                 log_scale_mean=-0.8)
+    else:
+        sc = scenegen.tiny_scene(n, seed, sh_degree=(seed % 2) * 3)
+    if opac_boost:
+        logit = np.log(sc["opacity"] / (1 - sc["opacity"])) + opac_boost
+        sc["opacity"] = (1 / (1 + np.exp(-logit))).astype(np.float32)
+    W = H = 8
+    r = oracle.render(sc, IDENT_POSE, TINY_INTR, W, H)
+    rec = oracle.project_all(sc, IDENT_POSE, TINY_INTR, W, H)
+    ref = product_form(rec, W, H)
+    flagged = set(r.var_pix.tolist())
+    for j in range(H):
+        for i in range(W):
+            if j * W + i in flagged:
+                continue
+            np.testing.assert_allclose(r.rgb[j, i], ref[j, i, :3], atol=1e-12)
+            assert r.depth[j, i] == pytest.approx(ref[j, i, 3], rel=1e-12, abs=1e-12)
+            assert r.alpha[j, i] == pytest.approx(ref[j, i, 4], abs=1e-12)
+    assert r.counters["pairs"] > 0
+    if opac_boost >= 3.0:
+        assert r.tfinal.min() < 1e-3   # the stop rule is exercised
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_permutation_invariance(seed):
+    sc = scenegen.tiny_scene(40, seed + 100, sh_degree=3)
+    perm = np.random.default_rng(seed).permutation(40)
+    sp = {k: (v[perm] if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
+    a = oracle.render(sc, IDENT_POSE, [20, 20, 16, 12], 32, 24)
+    b = oracle.render(sp, IDENT_POSE, [20, 20, 16, 12], 32, 24)
+    np.testing.assert_array_equal(a.rgb, b.rgb)
+    np.testing.assert_array_equal(a.depth, b.depth)
+
+
+def _workload0_render():
+    sc = scenegen.make_scene(0)
+    cams = scenegen.make_cameras(0)
+    return sc, cams, oracle.render(sc, cams["poses"][0], cams["intrinsics"][0], 64, 48)
+
+
+def test_invariants_workload0():
+    sc, cams, r = _workload0_render()
+    assert r.tfinal.min() >= TMIN and r.tfinal.max() <= 1.0
+    np.testing.assert_allclose(r.alpha, 1.0 - r.tfinal, atol=1e-12)
+    assert r.alpha.max() <= 1.0 - TMIN + 1e-12
+    rec = oracle.project_all(sc, cams["poses"][0], cams["intrinsics"][0], 64, 48)
+    vis = rec["visible"] > 0
+    cmax = max(rec["r"][vis].max(), rec["g"][vis].max(), rec["b"][vis].max())
+    assert np.all(r.rgb <= cmax * r.alpha[..., None] + 1e-12)
+    has = r.alpha > 0
+    assert r.depth[has].min() >= rec["z"][vis].min() - 1e-12
+    assert r.depth[has].max() <= rec["z"][vis].max() + 1e-12
+    assert np.all(r.depth[~has] == 0)
+    assert r.counters["unresolved"] == 0
+
+
+def _unflagged(*renders):
+    H, W = renders[0].depth.shape
+    m = np.ones(H * W, bool)
+    for r in renders:
+        m[r.var_pix] = False
+    return m.reshape(H, W)
+
+
+def test_rigid_motion_invariance():
+    sc, cams, a = _workload0_render()
+    R = Rotation.from_euler("xyz", [20, -35, 50], degrees=True)
+    t = np.array([1.5, -2.0, 0.75])
+    sc2 = dict(sc)
+    sc2["means"] = (R.apply(sc["means"].astype(np.float64)) + t).astype(np.float32)
+    q = sc["quats"].astype(np.float64)
+    qr = (R * Rotation.from_quat(q[:, [1, 2, 3, 0]])).as_quat()
+    sc2["quats"] = qr[:, [3, 0, 1, 2]].astype(np.float32)
+    pose = cams["poses"][0].astype(np.float64)
+    pose2 = np.concatenate([R.as_matrix() @ pose[:, :3], (R.apply(pose[:, 3]) + t)[:, None]], axis=1)
+    b = oracle.render(sc2, pose2.astype(np.float32), cams["intrinsics"][0], 64, 48)
+    m = _unflagged(a, b)
+    np.testing.assert_allclose(b.rgb[m], a.rgb[m], atol=1e-4)
+    np.testing.assert_allclose(b.alpha[m], a.alpha[m], atol=1e-4)
+    np.testing.assert_allclose(b.depth[m], a.depth[m], rtol=1e-5, atol=1e-6)
+
+
+# ------------------------------------------------------------- comparator ----
+
+def test_comparator_accepts_itself_and_rejects_planted_errors():
+    sc, cams, r = _workload0_render()
+    rep = oracle.compare(r, r.rgb, r.depth, r.alpha)
+    assert rep["failed"] == 0 and rep["max_abs_rgb"] == 0.0
+    rgb = r.rgb.copy()
+    rgb[10, 20, 1] += 3e-3
+    assert oracle.compare(r, rgb, r.depth, r.alpha)["failed"] == 1
+    dep = r.depth.copy()
+    j, i = np.argwhere(r.alpha > 0.5)[0]
+    dep[j, i] *= 1.002
+    assert oracle.compare(r, r.rgb, dep, r.alpha)["failed"] == 1
+    dep = r.depth.copy()
+    j, i = np.argwhere(r.alpha == 0)[0] if (r.alpha == 0).any() else (0, 0)
+    if r.alpha[j, i] == 0:
+        dep[j, i] = 0.5
+        assert oracle.compare(r, r.rgb, dep, r.alpha)["failed"] == 1
+
+
+def test_comparator_rescues_listed_alternatives():
+    sc, cams, r = _workload0_render()
+    assert len(r.var_pix) > 0
+    # replace every flagged pixel by its last listed alternative
+    rgb, dep, alp = r.rgb.copy(), r.depth.copy(), r.alpha.copy()
+    W = r.depth.shape[1]
+    changed = 0
+    for p in np.unique(r.var_pix):
+        rows = r.var_vals[r.var_pix == p]
+        v = rows[-1]
+        j, i = divmod(int(p), W)
+        if np.max(np.abs(v[:3] - rgb[j, i])) > 2e-3:
+            changed += 1
+        rgb[j, i], dep[j, i], alp[j, i] = v[:3], v[3], v[4]
+    rep = oracle.compare(r, rgb, dep, alp)
+    assert rep["failed"] == 0
+    assert rep["rescued"] >= changed
+
+
+def test_two_saturated_alternative_is_listed():
+    # The second of two alpha = 0.99 Gaussians sits within rounding of the
+    # stop threshold: a renderer that includes it is also accepted.
+    Y00 = 1.0 / (2.0 * math.sqrt(math.pi))
+    cols = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
+    sc = dict(means=np.array([[0, 0, 2.0], [0, 0, 3.0]], np.float32),
+              scales=np.full((2, 3), 0.25, np.float32),
+              quats=np.tile(np.array([1, 0, 0, 0], np.float32), (2, 1)),
+              opacity=np.ones(2, np.float32),
+              sh=((cols - 0.5) / Y00).astype(np.float32).reshape(2, 1, 3), sh_degree=0)
+    r = oracle.render(sc, IDENT_POSE, [50, 50, 32.5, 24.5], 64, 48)
+    rgb = r.rgb.copy()
+    c1 = float(sc["sh"][0, 0, 0]) * Y00 + 0.5
+    c2 = float(sc["sh"][1, 0, 1]) * Y00 + 0.5
+    rgb[24, 32, 1] += (1 - AMAX) * AMAX * c2
+    alp = r.alpha.copy()
+    alp[24, 32] += (1 - AMAX) * AMAX
+    dep = r.depth.copy()
+    dep[24, 32] = (AMAX * 2.0 + (1 - AMAX) * AMAX * 3.0) / alp[24, 32]
+    assert c1 > 0.99
+    rep = oracle.compare(r, rgb, dep, alp)
+    assert rep["failed"] == 0 and rep["rescued"] >= 1
