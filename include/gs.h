@@ -1,0 +1,183 @@
+/*
+ * gs.h -- C interface of the MI355X (gfx950) batched Gaussian-splat renderer.
+ *
+ * The library renders RGB and expected depth of many pinhole cameras over
+ * many 3D Gaussian-splat scenes, the renderer the paper drops into its
+ * vectorised simulator (Sec. 3.2 "3D Gaussian Splatting as a Drop-in
+ * Renderer": splats batch-rendered across environments; depth as a
+ * by-product of the same rasterisation, Fig. "Rendering RGB and Depth";
+ * thousands of environments over many scenes on one GPU, Sec. 3.3).
+ * The splat model is the cited 3DGS (Sec. 2.3): EWA projection with a
+ * 0.3 px^2 low-pass, SH colour, 16x16 tile binning sorted by tile and depth,
+ * front-to-back compositing with alpha clamped to 0.99, contributions below
+ * 1/255 skipped and the walk stopped before transmittance falls under 1e-4.
+ *
+ * Conventions
+ *   poses       camera-to-world [R | C], 3x4 row-major FP32, OpenCV axes
+ *               (x right, y down, z forward)
+ *   intrinsics  (fx, fy, cx, cy) FP32 in pixels; pixel (i, j) covers
+ *               [i, i+1) x [j, j+1), its centre is (i + 1/2, j + 1/2)
+ *   quaternions (w, x, y, z), any non-zero norm (normalised inside)
+ *   scales      linear (> 0); opacity linear in [0, 1]
+ *   sh          [n][(deg+1)^2][3], real SH with Condon-Shortley phase,
+ *               l-major, m = -l..l; colour = max(0, SH(d) + 0.5) with d the
+ *               unit direction from the camera centre to the mean
+ *   outputs     rgb [n_cams][H][W][3], depth [n_cams][H][W] (expected camera
+ *               z, 0 where nothing was accumulated), alpha [n_cams][H][W]
+ *               (accumulated weight = 1 - final transmittance), FP32
+ *
+ * Ownership: the library copies every scene it is given; callers own every
+ * pointer they pass. Device pointers are HIP device addresses on the
+ * context's device. Streams are hipStream_t passed as void* (NULL = the
+ * default stream).
+ *
+ * Errors: every call returns GS_OK (0) or a negative GS_ERR_* code and never
+ * throws; gs_last_error() describes the last failure of that context.
+ * Argument validation is synchronous. A context is not thread-safe: use one
+ * per thread or lock around it.
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gs_ctx gs_ctx;
+
+#define GS_OK 0
+#define GS_ERR_INVALID_ARG (-1)
+#define GS_ERR_BAD_SCENE (-2)
+#define GS_ERR_OOM (-3)
+#define GS_ERR_CAPACITY (-4)
+#define GS_ERR_HIP (-5)
+#define GS_ERR_BUSY (-6)
+#define GS_ERR_NOT_TRAINED (-7)
+
+#define GS_MEM_HOST 0
+#define GS_MEM_DEVICE 1
+
+#define GS_MODE_PLAIN 0   /* per-camera kernel sequence, eager launches */
+#define GS_MODE_BATCHED 1 /* all cameras in camera chunks, one launch per stage */
+
+typedef struct {
+    int64_t n;          /* number of Gaussians, >= 1 */
+    int32_t sh_degree;  /* 0..3 */
+    int32_t mem_kind;   /* GS_MEM_HOST or GS_MEM_DEVICE for all five arrays */
+    const float *means;   /* [n][3] world position (m) */
+    const float *scales;  /* [n][3] linear standard deviations (m), > 0 */
+    const float *quats;   /* [n][4] (w, x, y, z) */
+    const float *opacity; /* [n] in [0, 1] */
+    const float *sh;      /* [n][(sh_degree+1)^2][3] */
+} gs_scene_desc;
+
+typedef struct {
+    float near_plane;  /* Gaussians with camera z <= near_plane are dropped (default 0.2) */
+    float bg[3];       /* background colour added with the final transmittance (default 0) */
+    int32_t mode;      /* GS_MODE_PLAIN or GS_MODE_BATCHED (default BATCHED) */
+    int32_t tile_w;    /* raster tile width in pixels; 0 = tuned/default (16) */
+    int32_t tile_h;    /* raster tile height; 0 = tuned/default (16) */
+    int32_t lds_batch; /* Gaussians staged in LDS per batch; 0 = tuned/default (256) */
+    int32_t chunk_cams;/* BATCHED: cameras per chunk; 0 = tuned/default */
+    int32_t persistent;/* BATCHED: raster as a persistent work queue (1), a grid (0), -1 = tuned */
+    int32_t use_graph; /* BATCHED: capture the step into a HIP graph and replay it (1) */
+    int32_t reserved[5];
+} gs_render_opts;
+
+typedef struct {
+    int64_t visible;          /* (camera, Gaussian) pairs whose footprint meets the image */
+    int64_t instances;        /* (camera, tile, Gaussian) entries that were sorted */
+    int64_t instance_capacity;/* current instance buffer capacity */
+    int32_t regrows;          /* capacity regrowths during the last render */
+    int32_t graph_captures;   /* graphs captured by this context so far */
+    int32_t tile_w, tile_h, lds_batch, chunk_cams, persistent; /* choice actually used */
+    int32_t reserved;
+} gs_stats;
+
+/* sizeof of gs_scene_desc, gs_render_opts and gs_stats as compiled into the
+ * library (lets bindings check their struct layouts). Returns GS_OK. */
+int gs_abi_sizes(int32_t *scene_desc, int32_t *render_opts, int32_t *stats);
+
+/* Fill opts with the defaults listed in gs_render_opts. */
+void gs_default_opts(gs_render_opts *opts);
+
+/* Create a context on HIP device `hip_device`. *out receives the handle. */
+int gs_create(int hip_device, gs_ctx **out);
+
+/* Free every scene, workspace and captured graph of the context. */
+int gs_destroy(gs_ctx *ctx);
+
+/* Text of the last error of the context (valid until the next call). */
+const char *gs_last_error(const gs_ctx *ctx);
+
+/* Copy a scene into the library (synchronous). The library precomputes the
+ * factor M = R(q) S of the 3D covariance M M^T per Gaussian and stores the
+ * SH coefficients in a planar layout. Returns its id in *scene_id_out. Rejects n < 1, degree
+ * outside 0..3, null arrays, non-finite values (GS_ERR_BAD_SCENE). */
+int gs_upload_scene(gs_ctx *ctx, const gs_scene_desc *desc, int32_t *scene_id_out);
+
+/* Free a scene. GS_ERR_BUSY if a captured graph still references it. */
+int gs_release_scene(gs_ctx *ctx, int32_t scene_id);
+
+/* Number of Gaussians of a scene (or a negative error). */
+int64_t gs_scene_size(gs_ctx *ctx, int32_t scene_id);
+
+/*
+ * Render n_cams cameras.
+ *   scene_ids   HOST int32 [n_cams]: scene of each camera (environment)
+ *   poses       DEVICE float [n_cams][3][4]
+ *   intrinsics  DEVICE float [n_cams][4]
+ *   rgb, depth  DEVICE float outputs (layouts in the header comment)
+ *   alpha       DEVICE float [n_cams][H][W] or NULL
+ *   opts        NULL for defaults
+ * Work is enqueued on `stream`; the call then waits for that stream to read
+ * the device overflow flag of the instance buffers, regrows them and renders
+ * again if they overflowed, so outputs are complete when it returns GS_OK.
+ * In BATCHED mode with use_graph the first call for a given configuration
+ * (cameras, scenes, sizes, options, pointers) captures a HIP graph and later
+ * calls replay it.
+ */
+int gs_render_batch(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const float *poses,
+                    const float *intrinsics, int32_t width, int32_t height, float *rgb,
+                    float *depth, float *alpha, const gs_render_opts *opts, void *stream);
+
+/* Counters and choices of the last gs_render_batch of the context. */
+int gs_last_stats(gs_ctx *ctx, gs_stats *out);
+
+/* Set the instance-buffer capacity (entries) used by the next render; the
+ * library still grows it on overflow. Drops captured graphs. cap >= 1. */
+int gs_set_instance_capacity(gs_ctx *ctx, int64_t cap);
+
+/* Destroy every captured graph of the context (releases their scene refs). */
+int gs_clear_graphs(gs_ctx *ctx);
+
+/*
+ * Per-Gaussian projection of one camera, for checking the projection stage.
+ *   pose, intrinsics  HOST float [12], [4]
+ *   out               DEVICE float [n][16]: u, v, z, opacity, conic A B C
+ *                     (inverse 2D covariance incl. low-pass), r, g, b,
+ *                     x0, x1, y0, y1 (inclusive pixel-centre box of
+ *                     alpha >= 1/255; x0 > x1 when not visible), visible
+ * Synchronous.
+ */
+int gs_debug_project(gs_ctx *ctx, int32_t scene_id, const float *pose, const float *intrinsics,
+                     int32_t width, int32_t height, float near_plane, float *out);
+
+/*
+ * Time the batched form over candidate (tile shape, LDS batch, chunk size,
+ * persistent) choices for this camera batch and remember the fastest for
+ * later renders with the same (W, H, camera count, scene-size bucket).
+ * The table is appended to `cache_path` (JSON lines) when it is not NULL.
+ * Arguments as gs_render_batch (outputs are scratch). Synchronous.
+ */
+int gs_autotune(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const float *poses,
+                const float *intrinsics, int32_t width, int32_t height, float *rgb, float *depth,
+                const char *cache_path, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H */

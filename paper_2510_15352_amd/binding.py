@@ -1,0 +1,253 @@
+"""ctypes binding of libgsmi.so (the C interface in include/gs.h).
+
+Argument marshalling only: PyTorch provides device memory and the current
+HIP stream; every step of rendering runs in the library's HIP kernels.
+Importing works without a GPU (the library loads; nothing is launched), and
+every entry point raises if the library is missing -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgsmi.so")
+
+GS_OK = 0
+ERRORS = {-1: "GS_ERR_INVALID_ARG", -2: "GS_ERR_BAD_SCENE", -3: "GS_ERR_OOM",
+          -4: "GS_ERR_CAPACITY", -5: "GS_ERR_HIP", -6: "GS_ERR_BUSY", -7: "GS_ERR_NOT_TRAINED"}
+GS_MEM_HOST, GS_MEM_DEVICE = 0, 1
+GS_MODE_PLAIN, GS_MODE_BATCHED = 0, 1
+
+# every symbol include/gs.h declares
+EXPORTS = ("gs_abi_sizes", "gs_default_opts", "gs_create", "gs_destroy", "gs_last_error", "gs_upload_scene",
+           "gs_release_scene", "gs_scene_size", "gs_render_batch", "gs_last_stats",
+           "gs_debug_project", "gs_autotune", "gs_set_instance_capacity", "gs_clear_graphs")
+
+
+class GsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SceneDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("mem_kind", ctypes.c_int32),
+                ("means", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                ("opacity", ctypes.c_void_p), ("sh", ctypes.c_void_p)]
+
+
+class RenderOpts(ctypes.Structure):
+    _fields_ = [("near_plane", ctypes.c_float), ("bg", ctypes.c_float * 3), ("mode", ctypes.c_int32),
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("lds_batch", ctypes.c_int32), ("chunk_cams", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("visible", ctypes.c_int64), ("instances", ctypes.c_int64),
+                ("instance_capacity", ctypes.c_int64), ("regrows", ctypes.c_int32),
+                ("graph_captures", ctypes.c_int32), ("tile_w", ctypes.c_int32),
+                ("tile_h", ctypes.c_int32), ("lds_batch", ctypes.c_int32),
+                ("chunk_cams", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libgsmi.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python paper_2510_15352_amd/build.py` (there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, fp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    L.gs_default_opts.argtypes = [ctypes.POINTER(RenderOpts)]
+    L.gs_default_opts.restype = None
+    L.gs_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+    L.gs_destroy.argtypes = [vp]
+    L.gs_last_error.argtypes = [vp]
+    L.gs_last_error.restype = ctypes.c_char_p
+    L.gs_upload_scene.argtypes = [vp, ctypes.POINTER(SceneDesc), ctypes.POINTER(i32)]
+    L.gs_release_scene.argtypes = [vp, i32]
+    L.gs_scene_size.argtypes = [vp, i32]
+    L.gs_scene_size.restype = i64
+    L.gs_render_batch.argtypes = [vp, i32, vp, vp, vp, i32, i32, vp, vp, vp,
+                                  ctypes.POINTER(RenderOpts), vp]
+    L.gs_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.gs_debug_project.argtypes = [vp, i32, vp, vp, i32, i32, fp, vp]
+    L.gs_autotune.argtypes = [vp, i32, vp, vp, vp, i32, i32, vp, vp, ctypes.c_char_p, vp]
+    L.gs_set_instance_capacity.argtypes = [vp, i64]
+    L.gs_clear_graphs.argtypes = [vp]
+    for name in EXPORTS:
+        if not hasattr(L, name):
+            raise RuntimeError(f"{LIB_PATH} does not export {name}")
+    sizes = [ctypes.c_int32() for _ in range(3)]
+    L.gs_abi_sizes(*[ctypes.byref(s) for s in sizes])
+    mine = (ctypes.sizeof(SceneDesc), ctypes.sizeof(RenderOpts), ctypes.sizeof(Stats))
+    if tuple(s.value for s in sizes) != mine:
+        raise RuntimeError(f"struct layout mismatch: library {[s.value for s in sizes]}, "
+                           f"binding {list(mine)}")
+    _lib = L
+    return L
+
+
+def _stream_ptr(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f32(torch, a, device):
+    t = torch.as_tensor(a)
+    return t.to(device=device, dtype=torch.float32).contiguous()
+
+
+class Renderer:
+    """A gs_ctx on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the renderer runs only on the GPU")
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        rc = self.lib.gs_create(device, ctypes.byref(h))
+        if rc != GS_OK:
+            raise GsError(rc, "gs_create failed")
+        self.ctx = h
+        self._keep = {}
+
+    # ------------------------------------------------------------ errors --
+    def _check(self, rc):
+        if rc < 0:
+            raise GsError(rc, self.lib.gs_last_error(self.ctx).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.gs_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ scenes --
+    def upload_scene(self, scene: dict, device_copy: bool = False) -> int:
+        """Upload a scene (dict of FP32 arrays, see scenegen). With
+        device_copy the arrays are first placed in device memory and the
+        library reads them there (GS_MEM_DEVICE)."""
+        torch = self.torch
+        n = int(len(scene["opacity"]))
+        keys = ("means", "scales", "quats", "opacity", "sh")
+        if device_copy:
+            arrs = [_dev_f32(torch, scene[k], self.device) for k in keys]
+            ptrs = [a.data_ptr() for a in arrs]
+            kind = GS_MEM_DEVICE
+        else:
+            arrs = [np.ascontiguousarray(np.asarray(scene[k]), dtype=np.float32) for k in keys]
+            ptrs = [a.ctypes.data for a in arrs]
+            kind = GS_MEM_HOST
+        d = SceneDesc(n, int(scene["sh_degree"]), kind, *ptrs)
+        sid = ctypes.c_int32(-1)
+        self._check(self.lib.gs_upload_scene(self.ctx, ctypes.byref(d), ctypes.byref(sid)))
+        return sid.value
+
+    def release_scene(self, sid: int):
+        self._check(self.lib.gs_release_scene(self.ctx, sid))
+
+    def scene_size(self, sid: int) -> int:
+        return self._check(self.lib.gs_scene_size(self.ctx, sid))
+
+    # ------------------------------------------------------------ render --
+    def opts(self, mode="batched", tile=None, lds_batch=0, chunk_cams=0, persistent=-1,
+             use_graph=False, near=0.2, bg=(0.0, 0.0, 0.0)):
+        o = RenderOpts()
+        self.lib.gs_default_opts(ctypes.byref(o))
+        o.mode = GS_MODE_PLAIN if mode == "plain" else GS_MODE_BATCHED
+        if tile:
+            o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
+        o.lds_batch = int(lds_batch)
+        o.chunk_cams = int(chunk_cams)
+        o.persistent = int(persistent)
+        o.use_graph = int(bool(use_graph))
+        o.near_plane = float(near)
+        for i in range(3):
+            o.bg[i] = float(bg[i])
+        return o
+
+    def alloc_outputs(self, n_cams, width, height, alpha=True):
+        torch = self.torch
+        rgb = torch.empty((n_cams, height, width, 3), dtype=torch.float32, device=self.device)
+        depth = torch.empty((n_cams, height, width), dtype=torch.float32, device=self.device)
+        al = (torch.empty((n_cams, height, width), dtype=torch.float32, device=self.device)
+              if alpha else None)
+        return rgb, depth, al
+
+    def render(self, scene_ids, poses, intrinsics, width, height, out=None, alpha=True,
+               opts=None, **kw):
+        """Render; returns (rgb, depth, alpha) device tensors. `poses` and
+        `intrinsics` may be numpy or torch (moved to the device)."""
+        torch = self.torch
+        sids = np.ascontiguousarray(np.asarray(scene_ids, dtype=np.int32).reshape(-1))
+        n = len(sids)
+        P = poses if (torch.is_tensor(poses) and poses.is_cuda and poses.dtype == torch.float32
+                      and poses.is_contiguous()) else _dev_f32(torch, poses, self.device)
+        K = intrinsics if (torch.is_tensor(intrinsics) and intrinsics.is_cuda
+                           and intrinsics.dtype == torch.float32 and intrinsics.is_contiguous()) \
+            else _dev_f32(torch, intrinsics, self.device)
+        if P.numel() != n * 12 or K.numel() != n * 4:
+            raise ValueError("poses must be [n,3,4] and intrinsics [n,4]")
+        rgb, depth, al = out if out is not None else self.alloc_outputs(n, width, height, alpha)
+        o = opts if opts is not None else self.opts(**kw)
+        self._check(self.lib.gs_render_batch(
+            self.ctx, n, sids.ctypes.data, P.data_ptr(), K.data_ptr(), int(width), int(height),
+            rgb.data_ptr(), depth.data_ptr(), al.data_ptr() if al is not None else None,
+            ctypes.byref(o), _stream_ptr(torch)))
+        return rgb, depth, al
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self.lib.gs_last_stats(self.ctx, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_ if k != "reserved"}
+
+    def set_instance_capacity(self, cap: int):
+        self._check(self.lib.gs_set_instance_capacity(self.ctx, int(cap)))
+
+    def drop_graphs(self):
+        self._check(self.lib.gs_clear_graphs(self.ctx))
+
+    def debug_project(self, sid, pose, intr, width, height, near=0.2):
+        """Per-Gaussian projection records of one camera: [n, 16] numpy."""
+        torch = self.torch
+        n = self.scene_size(sid)
+        out = torch.empty((n, 16), dtype=torch.float32, device=self.device)
+        p = np.ascontiguousarray(np.asarray(pose, np.float32).reshape(12))
+        k = np.ascontiguousarray(np.asarray(intr, np.float32).reshape(4))
+        self._check(self.lib.gs_debug_project(self.ctx, sid, p.ctypes.data, k.ctypes.data,
+                                              int(width), int(height), float(near),
+                                              out.data_ptr()))
+        return out.cpu().numpy()
+
+    def autotune(self, scene_ids, poses, intrinsics, width, height, cache_path=None):
+        torch = self.torch
+        sids = np.ascontiguousarray(np.asarray(scene_ids, dtype=np.int32).reshape(-1))
+        n = len(sids)
+        P = _dev_f32(torch, poses, self.device)
+        K = _dev_f32(torch, intrinsics, self.device)
+        rgb, depth, _ = self.alloc_outputs(n, width, height, alpha=False)
+        self._check(self.lib.gs_autotune(self.ctx, n, sids.ctypes.data, P.data_ptr(),
+                                         K.data_ptr(), int(width), int(height), rgb.data_ptr(),
+                                         depth.data_ptr(),
+                                         cache_path.encode() if cache_path else None,
+                                         _stream_ptr(torch)))

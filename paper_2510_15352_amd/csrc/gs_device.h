@@ -1,0 +1,253 @@
+// Device-side building blocks of the renderer (gfx950, wave64).
+//
+// Everything here is FP32. The per-Gaussian projection and the per-pixel
+// compositing step are single inline functions used by every kernel form
+// (plain, batched, persistent, any tile shape), so all forms produce
+// bitwise-identical images.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gs {
+
+// Fixed rules of the splat renderer (cited 3DGS, Sec. 2.3 of the paper):
+// alpha clamp, skip threshold, stop threshold, low-pass, tangent clamp.
+constexpr float kAlphaMax = 0.99f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTMin = 1e-4f;
+constexpr float kLowPass = 0.3f;
+constexpr float kTanClamp = 1.3f;
+// sqrt(log2(e) / 2): folds the -1/2 of the Gaussian exponent and the change
+// to base 2 into the per-Gaussian factor of the quadratic form.
+constexpr float kHalfLog2e_sqrt = 0.84932180028801904272f;
+
+constexpr int kWave = 64;
+
+// Per-camera constants (step "camera setup"), one per chunk-local camera.
+struct CamParams {
+    float R[9];    // world -> camera rotation (row-major), R_wc = R_cw^T
+    float t[3];    // world -> camera translation, t_wc = -R_wc C
+    float C[3];    // camera centre in the world frame
+    float fx, fy, cx, cy;
+    float lxn, lxp, lyn, lyp;  // clamped tangent range of x/z and y/z
+    float pad[9];
+};
+static_assert(sizeof(CamParams) == 32 * 4, "CamParams is 128 B");
+
+// Device view of one uploaded scene (structure of arrays).
+struct SceneDev {
+    const float4 *pos_op;  // [n] (mx, my, mz, opacity)
+    const float4 *m01;     // [n] M = R(q) S row-major: (m00, m01, m02, m10)
+    const float4 *m23;     // [n] (m11, m12, m20, m21)
+    const float *m8;       // [n] m22
+    const float *sh;       // [(deg+1)^2 * 3][n] planar
+    int64_t n;
+    int32_t deg;
+    int32_t pad;
+};
+
+// One projection work item: Gaussians [g0, g0 + 256) of `scene` seen by the
+// chunk-local cameras [cam0, cam0 + ncam).
+struct ProjItem {
+    int32_t scene;
+    int32_t g0;
+    int32_t cam0;
+    int32_t ncam;
+};
+
+// Raster-ready record of a visible (camera, Gaussian) pair, 48 bytes:
+//   A = (u, v, e_x, e_y)   with  e = e_x dx + e_y dy
+//   B = (f_y, opacity, r, g)     f = f_y dy
+//   C = (b, z, 0, 0)
+// so that alpha = min(0.99, o * 2^-(e^2 + f^2)) at offset (dx, dy).
+// (e, f) is the upper-triangular factor U of the conic, U^T U = Sigma'^-1,
+// scaled by sqrt(log2(e)/2): a sum of squares, free of the cancellation of
+// the expanded quadratic form for thin, magnified Gaussians.
+
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    const uint32_t lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Real SH (Condon-Shortley phase) colour, degree DEG, direction (x, y, z)
+// unit; k[(l^2 + l + m) * 3 + c]. Polynomial forms of Y_lm derived from
+// Y_lm = sqrt2 K_l^|m| P_l^|m|(cos th) {cos, sin}(|m| phi),
+// K_l^m = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!).
+template <int DEG>
+__device__ __forceinline__ void sh_colour(const float *k, float x, float y, float z, float &r,
+                                          float &g, float &b)
+{
+    // l = 0: 1/(2 sqrt(pi))
+    float y00 = 0.28209479177387814f;
+    float acc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] = y00 * k[c];
+    if (DEG >= 1) {
+        // l = 1: sqrt(3/(4 pi)) * (-y, z, -x)
+        const float c1 = 0.48860251190291992f;
+        float b1[3] = {-c1 * y, c1 * z, -c1 * x};
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c] = fmaf(b1[m], k[(1 + m) * 3 + c], acc[c]);
+    }
+    if (DEG >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        // l = 2: (1/2)sqrt(15/pi) xy, -(1/2)sqrt(15/pi) yz,
+        //        (1/4)sqrt(5/pi)(2zz - xx - yy), -(1/2)sqrt(15/pi) xz,
+        //        (1/4)sqrt(15/pi)(xx - yy)
+        const float c2a = 1.09254843059207907f;
+        const float c2b = 0.31539156525252001f;
+        const float c2c = 0.54627421529603954f;
+        float b2[5] = {c2a * x * y, -c2a * y * z, c2b * (2.0f * zz - xx - yy), -c2a * x * z,
+                       c2c * (xx - yy)};
+#pragma unroll
+        for (int m = 0; m < 5; ++m)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c] = fmaf(b2[m], k[(4 + m) * 3 + c], acc[c]);
+        if (DEG >= 3) {
+            // l = 3: -(1/4)sqrt(35/(2pi)) y(3xx - yy), (1/2)sqrt(105/pi) xyz,
+            //        -(1/4)sqrt(21/(2pi)) y(4zz - xx - yy),
+            //        (1/4)sqrt(7/pi) z(2zz - 3xx - 3yy),
+            //        -(1/4)sqrt(21/(2pi)) x(4zz - xx - yy),
+            //        (1/4)sqrt(105/pi) z(xx - yy), -(1/4)sqrt(35/(2pi)) x(xx - 3yy)
+            const float c3a = 0.59004358992664352f;
+            const float c3b = 2.89061144264055406f;
+            const float c3c = 0.45704579946446574f;
+            const float c3d = 0.37317633259011540f;
+            const float c3e = 1.44530572132027703f;
+            float b3[7] = {-c3a * y * (3.0f * xx - yy),
+                           c3b * x * y * z,
+                           -c3c * y * (4.0f * zz - xx - yy),
+                           c3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy),
+                           -c3c * x * (4.0f * zz - xx - yy),
+                           c3e * z * (xx - yy),
+                           -c3a * x * (xx - 3.0f * yy)};
+#pragma unroll
+            for (int m = 0; m < 7; ++m)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[c] = fmaf(b3[m], k[(9 + m) * 3 + c], acc[c]);
+        }
+    }
+    r = fmaxf(acc[0] + 0.5f, 0.0f);
+    g = fmaxf(acc[1] + 0.5f, 0.0f);
+    b = fmaxf(acc[2] + 0.5f, 0.0f);
+}
+
+struct Projected {
+    float4 A, B, C;
+    int x0, x1, y0, y1;  // inclusive pixel-centre box
+};
+
+// EWA projection of one Gaussian into one camera (steps: cull at the near
+// plane; T = J W; Sigma' = T M M^T T^T + 0.3 I with M = R(q) S; conic
+// factor; exact footprint box of alpha >= 1/255). Returns false when the
+// Gaussian is behind the near plane, too transparent or off-image.
+// Colour is filled by the caller (it needs the SH coefficients).
+__device__ __forceinline__ bool project_gaussian(const CamParams &cam, float4 pos_op, float4 m01,
+                                                 float4 m23, float m22, float near, int W, int H,
+                                                 Projected &P)
+{
+    const float mx = pos_op.x, my = pos_op.y, mz = pos_op.z, o = pos_op.w;
+    const float x = fmaf(cam.R[0], mx, fmaf(cam.R[1], my, fmaf(cam.R[2], mz, cam.t[0])));
+    const float y = fmaf(cam.R[3], mx, fmaf(cam.R[4], my, fmaf(cam.R[5], mz, cam.t[1])));
+    const float z = fmaf(cam.R[6], mx, fmaf(cam.R[7], my, fmaf(cam.R[8], mz, cam.t[2])));
+    if (!(z > near) || !(o >= kAlphaMin)) return false;
+    const float iz = 1.0f / z;
+    const float xz = x * iz, yz = y * iz;
+    const float u = fmaf(cam.fx, xz, cam.cx);
+    const float v = fmaf(cam.fy, yz, cam.cy);
+    const float txc = fminf(fmaxf(xz, cam.lxn), cam.lxp);
+    const float tyc = fminf(fmaxf(yz, cam.lyn), cam.lyp);
+    const float j00 = cam.fx * iz, j02 = -cam.fx * txc * iz;
+    const float j11 = cam.fy * iz, j12 = -cam.fy * tyc * iz;
+    // rows of T = J W
+    const float t00 = fmaf(j02, cam.R[6], j00 * cam.R[0]);
+    const float t01 = fmaf(j02, cam.R[7], j00 * cam.R[1]);
+    const float t02 = fmaf(j02, cam.R[8], j00 * cam.R[2]);
+    const float t10 = fmaf(j12, cam.R[6], j11 * cam.R[3]);
+    const float t11 = fmaf(j12, cam.R[7], j11 * cam.R[4]);
+    const float t12 = fmaf(j12, cam.R[8], j11 * cam.R[5]);
+    // M = R(q) S, row-major m[3][3]
+    const float M00 = m01.x, M01 = m01.y, M02 = m01.z, M10 = m01.w;
+    const float M11 = m23.x, M12 = m23.y, M20 = m23.z, M21 = m23.w, M22 = m22;
+    // p = T_0 M, q = T_1 M  (so Sigma'_0 = [[p.p, p.q], [p.q, q.q]])
+    const float p0 = fmaf(t00, M00, fmaf(t01, M10, t02 * M20));
+    const float p1 = fmaf(t00, M01, fmaf(t01, M11, t02 * M21));
+    const float p2 = fmaf(t00, M02, fmaf(t01, M12, t02 * M22));
+    const float q0 = fmaf(t10, M00, fmaf(t11, M10, t12 * M20));
+    const float q1 = fmaf(t10, M01, fmaf(t11, M11, t12 * M21));
+    const float q2 = fmaf(t10, M02, fmaf(t11, M12, t12 * M22));
+    const float pp = fmaf(p0, p0, fmaf(p1, p1, p2 * p2));
+    const float qq = fmaf(q0, q0, fmaf(q1, q1, q2 * q2));
+    const float pq = fmaf(p0, q0, fmaf(p1, q1, p2 * q2));
+    // det(Sigma') = |p x q|^2 + 0.3 (|p|^2 + |q|^2) + 0.09 (Lagrange identity)
+    const float cx_ = p1 * q2 - p2 * q1, cy_ = p2 * q0 - p0 * q2, cz_ = p0 * q1 - p1 * q0;
+    const float cross2 = fmaf(cx_, cx_, fmaf(cy_, cy_, cz_ * cz_));
+    const float a = pp + kLowPass, c = qq + kLowPass, b = pq;
+    const float det = fmaf(kLowPass, pp + qq, cross2) + kLowPass * kLowPass;
+    if (!(det > 0.0f)) return false;
+    // upper factor of Sigma'^-1 = [[c, -b], [-b, a]] / det:
+    //   e = sqrt(c/det) dx - b/sqrt(c det) dy,  f = dy / sqrt(c)
+    const float rc = rsqrtf(c);
+    const float rdet = rsqrtf(det);
+    const float ex = c * rc * rdet;  // sqrt(c) / sqrt(det)
+    const float ey = -b * rc * rdet;
+    const float fy = rc;
+    // footprint: alpha >= 1/255 <=> e^2 + f^2 <= r2 = 2 ln(o / alpha_min);
+    // box half-extents r sqrt(Sigma'_xx), r sqrt(Sigma'_yy), widened a little
+    // so that FP32 rounding never drops a contributing pixel.
+    const float r2 = fmaxf(2.0f * logf(o * 255.0f), 0.0f);
+    const float ext_x = fmaf(sqrtf(r2 * a), 1.001f, 0.01f);
+    const float ext_y = fmaf(sqrtf(r2 * c), 1.001f, 0.01f);
+    const float fx0 = ceilf(u - ext_x - 0.5f), fx1 = floorf(u + ext_x - 0.5f);
+    const float fy0 = ceilf(v - ext_y - 0.5f), fy1 = floorf(v + ext_y - 0.5f);
+    if (!(fx0 <= fx1) || !(fy0 <= fy1) || !(fx0 <= (float)(W - 1)) || !(fx1 >= 0.0f) ||
+        !(fy0 <= (float)(H - 1)) || !(fy1 >= 0.0f))
+        return false;
+    P.x0 = (int)fmaxf(fx0, 0.0f);
+    P.x1 = (int)fminf(fx1, (float)(W - 1));
+    P.y0 = (int)fmaxf(fy0, 0.0f);
+    P.y1 = (int)fminf(fy1, (float)(H - 1));
+    P.A = make_float4(u, v, ex * kHalfLog2e_sqrt, ey * kHalfLog2e_sqrt);
+    P.B = make_float4(fy * kHalfLog2e_sqrt, o, 0.0f, 0.0f);
+    P.C = make_float4(0.0f, z, 0.0f, 0.0f);
+    return true;
+}
+
+// Per-pixel state of the front-to-back walk.
+struct Pixel {
+    float T, r, g, b, zw;
+    bool done;
+};
+
+// One step of the walk for one (pixel, Gaussian) pair: alpha clamped to
+// 0.99; skipped below 1/255; the walk stops (without this Gaussian) when the
+// new transmittance would fall under 1e-4; otherwise weight alpha T is
+// accumulated into colour and depth.
+__device__ __forceinline__ void composite(Pixel &s, float px, float py, float4 A, float4 B,
+                                          float2 C)
+{
+    const float dx = px - A.x, dy = py - A.y;
+    const float e = fmaf(A.w, dy, A.z * dx);
+    const float f = B.x * dy;
+    const float q = fmaf(e, e, f * f);
+    const float alpha = fminf(kAlphaMax, B.y * __builtin_amdgcn_exp2f(-q));
+    if (alpha >= kAlphaMin) {
+        const float Tn = s.T * (1.0f - alpha);
+        if (Tn < kTMin) {
+            s.done = true;
+        } else {
+            const float w = alpha * s.T;
+            s.r = fmaf(w, B.z, s.r);
+            s.g = fmaf(w, B.w, s.g);
+            s.b = fmaf(w, C.x, s.b);
+            s.zw = fmaf(w, C.y, s.zw);
+            s.T = Tn;
+        }
+    }
+}
+
+}  // namespace gs

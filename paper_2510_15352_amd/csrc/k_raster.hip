@@ -1,0 +1,233 @@
+// Tile binning (instance emission, tile ranges) and the LDS-staged
+// front-to-back rasteriser, as a one-block-per-tile grid or a persistent
+// work queue.
+#include "gs_device.h"
+#include "kernels.h"
+
+namespace gs {
+
+// ------------------------------------------------------------------ emit --
+// For the i-th record in (camera, depth, index) order write one instance per
+// overlapped tile: key = camera * tiles_per_cam + tile, value = slot.
+// Positions beyond the capacity are dropped (the overflow flag is raised by
+// k_finalize_counts and the host renders again with larger buffers).
+__global__ __launch_bounds__(256) void k_emit(const uint64_t *__restrict__ dkeys,
+                                              const uint32_t *__restrict__ dvals,
+                                              const uint32_t *__restrict__ n_vis,
+                                              const uint32_t *__restrict__ ioff,
+                                              const uint2 *__restrict__ rect, int tw, int th,
+                                              int tiles_x, int tiles_per_cam, uint32_t cap,
+                                              uint32_t *__restrict__ ikeys,
+                                              uint32_t *__restrict__ ivals)
+{
+    const uint32_t n = *n_vis;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t slot = dvals[i];
+        const uint32_t cl = (uint32_t)(dkeys[i] >> 31);
+        const uint2 r = rect[slot];
+        const int tx0 = (int)(r.x & 0xffffu) / tw, tx1 = (int)(r.x >> 16) / tw;
+        const int ty0 = (int)(r.y & 0xffffu) / th, ty1 = (int)(r.y >> 16) / th;
+        uint32_t o = ioff[i];
+        const uint32_t kbase = cl * (uint32_t)tiles_per_cam;
+        for (int ty = ty0; ty <= ty1; ++ty)
+            for (int tx = tx0; tx <= tx1; ++tx, ++o)
+                if (o < cap) {
+                    ikeys[o] = kbase + (uint32_t)(ty * tiles_x + tx);
+                    ivals[o] = slot;
+                }
+    }
+}
+
+// counts[0] = visible pairs, counts[1] = instances, counts[2] = instances
+// kept (min(instances, cap)); flags accumulate over the chunks of a render.
+__global__ void k_finalize_counts(uint32_t *counts, uint32_t cap, RenderFlags *flags)
+{
+    const uint32_t inst = counts[1];
+    counts[2] = inst < cap ? inst : cap;
+    if (inst > cap) flags->overflow = 1;
+    if (inst > flags->max_inst) flags->max_inst = inst;
+    flags->visible += counts[0];
+    flags->instances += inst;
+}
+
+__global__ void k_zero_u32(uint32_t *p, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// -------------------------------------------------------------- ranges --
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ ikeys,
+                                                const uint32_t *__restrict__ n_dev,
+                                                uint2 *__restrict__ ranges)
+{
+    const uint32_t n = *n_dev;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t k = ikeys[i];
+        if (i == 0 || ikeys[i - 1] != k) ranges[k].x = i;
+        if (i + 1 == n || ikeys[i + 1] != k) ranges[k].y = i + 1;
+    }
+}
+
+// -------------------------------------------------------------- raster --
+template <int TW, int TH, int B>
+__device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &a, float4 *sA,
+                                            float4 *sB, float2 *sC)
+{
+    constexpr int NT = TW * TH;
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int lx = (int)threadIdx.x % TW, ly = (int)threadIdx.x / TW;
+    const int pxi = tx * TW + lx, pyi = ty * TH + ly;
+    const bool inside = pxi < a.W && pyi < a.H;
+    const float px = (float)pxi + 0.5f, py = (float)pyi + 0.5f;
+    const uint2 rg = a.ranges[(uint32_t)cl * (uint32_t)a.tiles_per_cam + (uint32_t)tile];
+    Pixel s;
+    s.T = 1.0f; s.r = 0.0f; s.g = 0.0f; s.b = 0.0f; s.zw = 0.0f;
+    s.done = !inside;
+    for (uint32_t base = rg.x; base < rg.y; base += B) {
+        const int cnt = (int)min((uint32_t)B, rg.y - base);
+        __syncthreads();
+        for (int j = (int)threadIdx.x; j < cnt; j += NT) {
+            const uint32_t slot = a.ivals[base + j];
+            sA[j] = a.recA[slot];
+            sB[j] = a.recB[slot];
+            const float4 c = a.recC[slot];
+            sC[j] = make_float2(c.x, c.y);
+        }
+        __syncthreads();
+        if (!s.done) {
+            for (int j = 0; j < cnt; ++j) {
+                composite(s, px, py, sA[j], sB[j], sC[j]);
+                if (s.done) break;
+            }
+        }
+        if (__syncthreads_count(!s.done) == 0) break;
+    }
+    if (inside) {
+        const int64_t cg = a.cam_global[cl];
+        const int64_t pix = (cg * a.H + pyi) * (int64_t)a.W + pxi;
+        const float accw = 1.0f - s.T;
+        a.rgb[pix * 3 + 0] = fmaf(s.T, a.bg_r, s.r);
+        a.rgb[pix * 3 + 1] = fmaf(s.T, a.bg_g, s.g);
+        a.rgb[pix * 3 + 2] = fmaf(s.T, a.bg_b, s.b);
+        a.depth[pix] = accw > 0.0f ? s.zw / accw : 0.0f;
+        if (a.alpha) a.alpha[pix] = accw;
+    }
+}
+
+template <int TW, int TH, int B>
+__global__ __launch_bounds__(TW *TH) void k_raster(RasterArgs a)
+{
+    __shared__ float4 sA[B], sB[B];
+    __shared__ float2 sC[B];
+    raster_tile<TW, TH, B>((int)blockIdx.y, (int)blockIdx.x, a, sA, sB, sC);
+}
+
+// Persistent form: a grid sized to the resident capacity pulls
+// (camera, tile) items from a device counter until they run out.
+template <int TW, int TH, int B>
+__global__ __launch_bounds__(TW *TH) void k_raster_persistent(RasterArgs a, uint32_t *queue,
+                                                              uint32_t n_items)
+{
+    __shared__ float4 sA[B], sB[B];
+    __shared__ float2 sC[B];
+    __shared__ uint32_t s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(queue, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if (item >= n_items) break;
+        raster_tile<TW, TH, B>((int)(item / (uint32_t)a.tiles_per_cam),
+                               (int)(item % (uint32_t)a.tiles_per_cam), a, sA, sB, sC);
+    }
+}
+
+// --------------------------------------------------------------- launch --
+void launch_emit(const uint64_t *dkeys, const uint32_t *dvals, const uint32_t *n_vis,
+                 const uint32_t *ioff, const uint2 *rect, int tw, int th, int tiles_x,
+                 int tiles_per_cam, uint32_t cap, uint32_t *ikeys, uint32_t *ivals,
+                 uint32_t n_max, hipStream_t st)
+{
+    uint32_t blocks = (n_max + 255) / 256;
+    blocks = blocks < 1 ? 1 : (blocks > 16384 ? 16384 : blocks);
+    hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(256), 0, st, dkeys, dvals, n_vis, ioff, rect, tw,
+                       th, tiles_x, tiles_per_cam, cap, ikeys, ivals);
+}
+
+void launch_finalize_counts(uint32_t *counts, uint32_t cap, RenderFlags *flags, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_finalize_counts, dim3(1), dim3(1), 0, st, counts, cap, flags);
+}
+
+void launch_zero_u32(uint32_t *p, uint64_t n, hipStream_t st)
+{
+    if (n == 0) return;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+}
+
+void launch_ranges(const uint32_t *ikeys, const uint32_t *n_dev, uint2 *ranges, uint32_t n_max,
+                   hipStream_t st)
+{
+    uint32_t blocks = (n_max + 255) / 256;
+    blocks = blocks < 1 ? 1 : (blocks > 16384 ? 16384 : blocks);
+    hipLaunchKernelGGL(k_ranges, dim3(blocks), dim3(256), 0, st, ikeys, n_dev, ranges);
+}
+
+#define GS_RASTER_CASES(X) \
+    X(16, 16, 64) X(16, 16, 128) X(16, 16, 256) \
+    X(32, 8, 64) X(32, 8, 128) X(32, 8, 256) \
+    X(8, 8, 64) X(16, 8, 64) X(16, 8, 128) \
+    X(32, 16, 128) X(32, 16, 256)
+
+bool raster_supported(int tw, int th, int b)
+{
+#define X(TW_, TH_, B_) if (tw == TW_ && th == TH_ && b == B_) return true;
+    GS_RASTER_CASES(X)
+#undef X
+    return false;
+}
+
+int raster_occupancy(int tw, int th, int b)
+{
+    int blocks = 0;
+#define X(TW_, TH_, B_)                                                                       \
+    if (tw == TW_ && th == TH_ && b == B_) {                                                  \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(                                     \
+                &blocks, (const void *)k_raster_persistent<TW_, TH_, B_>, TW_ * TH_, 0) !=    \
+            hipSuccess)                                                                       \
+            blocks = 1;                                                                       \
+    }
+    GS_RASTER_CASES(X)
+#undef X
+    return blocks < 1 ? 1 : blocks;
+}
+
+void launch_raster(int tw, int th, int b, bool persistent, const RasterArgs &a, int n_cams,
+                   uint32_t *queue, int persistent_blocks, hipStream_t st)
+{
+    const int tiles = a.tiles_per_cam;
+    const uint32_t n_items = (uint32_t)tiles * (uint32_t)n_cams;
+#define X(TW_, TH_, B_)                                                                          \
+    if (tw == TW_ && th == TH_ && b == B_) {                                                     \
+        if (persistent) {                                                                        \
+            launch_zero_u32(queue, 1, st);                                                       \
+            int blocks = persistent_blocks;                                                      \
+            if ((uint32_t)blocks > n_items) blocks = (int)n_items;                               \
+            if (blocks < 1) blocks = 1;                                                          \
+            hipLaunchKernelGGL((k_raster_persistent<TW_, TH_, B_>), dim3(blocks),               \
+                               dim3(TW_ * TH_), 0, st, a, queue, n_items);                       \
+        } else {                                                                                 \
+            hipLaunchKernelGGL((k_raster<TW_, TH_, B_>), dim3(tiles, n_cams), dim3(TW_ * TH_), 0, \
+                               st, a);                                                           \
+        }                                                                                        \
+        return;                                                                                  \
+    }
+    GS_RASTER_CASES(X)
+#undef X
+}
+
+}  // namespace gs

@@ -1,0 +1,83 @@
+// Host-side launchers of the renderer's HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gs {
+
+struct CamParams;
+struct SceneDev;
+struct ProjItem;
+
+// Device flags of one render: instance-buffer overflow, largest instance
+// count of a chunk, and visible pairs / instances summed over the chunks.
+struct RenderFlags {
+    int32_t overflow;
+    uint32_t max_inst;
+    unsigned long long visible;
+    unsigned long long instances;
+};
+
+struct ScanTemp {
+    uint32_t *partial;  // >= 1024 entries
+};
+
+struct SortTemp {
+    uint32_t *hist;  // >= 256 * 1024 entries
+    ScanTemp scan;
+};
+
+struct RasterArgs {
+    const uint2 *ranges;   // [n_cams * tiles_per_cam] (start, end) into ivals
+    const uint32_t *ivals; // tile-sorted instance values (record slots)
+    const float4 *recA, *recB, *recC;
+    const int32_t *cam_global;  // chunk-local -> batch camera index
+    int tiles_x, tiles_per_cam, W, H;
+    float bg_r, bg_g, bg_b;
+    float *rgb, *depth, *alpha;
+};
+
+void launch_scene_prep(const float *means, const float *scales, const float *quats,
+                       const float *opacity, const float *sh, int64_t n, int ncoef, float4 *pos_op,
+                       float4 *m01, float4 *m23, float *m8, float *sh_planar, int *bad,
+                       hipStream_t st);
+void launch_camera_setup(const float *poses, const float *intr, const int32_t *cam_global,
+                         int n_cams, int W, int H, CamParams *out, hipStream_t st);
+void launch_project(int deg, const ProjItem *items, int n_items, const SceneDev *scenes,
+                    const CamParams *cams, const uint32_t *cam_slot, float near, int W, int H,
+                    float4 *recA, float4 *recB, float4 *recC, uint2 *rect, uint64_t *vis,
+                    hipStream_t st);
+void launch_compact(const uint64_t *vis, const uint32_t *word_off, uint32_t n_words,
+                    const uint32_t *cam_slot, int n_cams, const float4 *recC, uint64_t *keys,
+                    uint32_t *vals, hipStream_t st);
+void launch_debug_project(const SceneDev &sc, const CamParams *cam, float near, int W, int H,
+                          float *out, hipStream_t st);
+
+void scan_u32(const uint32_t *in, const uint32_t *n_dev, uint32_t n_max, uint32_t *out,
+              uint32_t *total_out, const ScanTemp &tmp, hipStream_t st);
+void scan_popcount(const uint64_t *words, uint32_t n_words, uint32_t *out, uint32_t *total_out,
+                   const ScanTemp &tmp, hipStream_t st);
+void scan_tile_counts(const uint32_t *vals, const uint2 *rect, int tw, int th,
+                      const uint32_t *n_dev, uint32_t n_max, uint32_t *out, uint32_t *total_out,
+                      const ScanTemp &tmp, hipStream_t st);
+// Return 0 if the sorted data ended in (k0, v0), 1 if in (k1, v1).
+int radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, const uint32_t *n_dev,
+                   uint32_t n_max, int bits, const SortTemp &tmp, hipStream_t st);
+int radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *n_dev,
+                   uint32_t n_max, int bits, const SortTemp &tmp, hipStream_t st);
+
+void launch_emit(const uint64_t *dkeys, const uint32_t *dvals, const uint32_t *n_vis,
+                 const uint32_t *ioff, const uint2 *rect, int tw, int th, int tiles_x,
+                 int tiles_per_cam, uint32_t cap, uint32_t *ikeys, uint32_t *ivals,
+                 uint32_t n_max, hipStream_t st);
+void launch_finalize_counts(uint32_t *counts, uint32_t cap, RenderFlags *flags, hipStream_t st);
+void launch_zero_u32(uint32_t *p, uint64_t n, hipStream_t st);
+void launch_ranges(const uint32_t *ikeys, const uint32_t *n_dev, uint2 *ranges, uint32_t n_max,
+                   hipStream_t st);
+bool raster_supported(int tw, int th, int b);
+int raster_occupancy(int tw, int th, int b);
+void launch_raster(int tw, int th, int b, bool persistent, const RasterArgs &a, int n_cams,
+                   uint32_t *queue, int persistent_blocks, hipStream_t st);
+
+}  // namespace gs

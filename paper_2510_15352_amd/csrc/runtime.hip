@@ -1,0 +1,910 @@
+// Host runtime behind include/gs.h: scene store, camera-batch planner,
+// workspace with device-side capacity checks, HIP-graph cache, autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/gs.h"
+#include "gs_device.h"
+#include "kernels.h"
+
+using namespace gs;
+
+namespace {
+
+struct GsError : std::runtime_error {
+    int code;
+    GsError(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIP_CHECK(expr)                                                                      \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            throw GsError(e_ == hipErrorOutOfMemory ? GS_ERR_OOM : GS_ERR_HIP,               \
+                          std::string(#expr) + ": " + hipGetErrorString(e_));                \
+    } while (0)
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    // Grow to at least `count` elements (contents are not preserved).
+    bool reserve(size_t count)
+    {
+        if (count <= n && p) return false;
+        release();
+        size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        HIP_CHECK(hipMalloc((void **)&p, bytes));
+        n = std::max<size_t>(count, 1);
+        return true;
+    }
+};
+
+struct Scene {
+    int64_t n = 0;
+    int deg = 0;
+    DevBuf<float4> pos_op, m01, m23;
+    DevBuf<float> m8, sh;
+    int graph_refs = 0;
+};
+
+using DevFlags = RenderFlags;
+
+struct Choice {
+    int tw = 16, th = 16, batch = 256, chunk = 512, persistent = 0;
+};
+
+struct Chunk {
+    int start = 0, count = 0;  // positions in the plan's camera order
+    uint64_t slots = 0;        // visibility slots (sum of per-camera scene sizes, 64-aligned)
+    int item_off[4] = {0, 0, 0, 0}, item_cnt[4] = {0, 0, 0, 0};
+};
+
+struct Plan {
+    int n_cams = 0, W = 0, H = 0;
+    Choice ch;
+    int tiles_x = 0, tiles_y = 0, tiles_per_cam = 0;
+    std::vector<int32_t> order;     // batch camera indices sorted by (scene, index)
+    std::vector<uint32_t> cam_slot; // per order position, slot base inside its chunk
+    std::vector<ProjItem> items;    // per chunk, grouped by SH degree
+    std::vector<Chunk> chunks;
+    std::vector<int32_t> scenes_used;
+    uint64_t max_slots = 0;
+    int max_chunk_cams = 0;
+    DevBuf<int32_t> d_order;
+    DevBuf<uint32_t> d_cam_slot;
+    DevBuf<ProjItem> d_items;
+};
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<int32_t> scenes;
+    std::unique_ptr<Plan> plan;
+};
+
+}  // namespace
+
+struct gs_ctx {
+    int device = 0;
+    int cu_count = 0;
+    std::string err;
+    std::vector<std::unique_ptr<Scene>> scenes;
+    DevBuf<SceneDev> d_scenes;
+    bool scenes_dirty = true;
+
+    // workspace
+    DevBuf<float4> recA, recB, recC;
+    DevBuf<uint2> rect;
+    DevBuf<uint64_t> vis;
+    DevBuf<uint32_t> word_off;
+    DevBuf<uint64_t> dkeys[2];
+    DevBuf<uint32_t> dvals[2];
+    DevBuf<uint32_t> ioff;
+    DevBuf<uint32_t> ikeys[2], ivals[2];
+    DevBuf<uint2> ranges;
+    DevBuf<CamParams> cams;
+    DevBuf<uint32_t> counts;  // [0] visible, [1] instances, [2] kept
+    DevBuf<DevFlags> flags;
+    DevBuf<uint32_t> queue;
+    DevBuf<uint32_t> scan_partial, sort_hist;
+    DevBuf<float> dbg_pose;
+    uint64_t inst_cap = 0;
+    int generation = 0;  // bumps whenever a workspace buffer moves
+
+    DevFlags *host_flags = nullptr;  // pinned
+    hipStream_t capture_stream = nullptr;
+
+    std::map<std::string, std::unique_ptr<GraphEntry>> graphs;
+    std::map<std::string, Choice> tuned;
+    gs_stats last{};
+    int graph_captures = 0;
+};
+
+namespace {
+
+int fail(gs_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+template <class F>
+int guarded(gs_ctx *ctx, F &&f)
+{
+    try {
+        return f();
+    } catch (const GsError &e) {
+        return fail(ctx, e.code, e.what());
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, GS_ERR_OOM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(ctx, GS_ERR_HIP, e.what());
+    } catch (...) {
+        return fail(ctx, GS_ERR_HIP, "unknown failure");
+    }
+}
+
+uint64_t round64(uint64_t x) { return (x + 63) & ~uint64_t(63); }
+
+int bits_for(uint64_t n_values)
+{
+    int b = 0;
+    while (b < 63 && (uint64_t(1) << b) < n_values) ++b;
+    return b;
+}
+
+void sync_scene_table(gs_ctx *ctx)
+{
+    if (!ctx->scenes_dirty) return;
+    std::vector<SceneDev> tab(std::max<size_t>(ctx->scenes.size(), 1));
+    for (size_t i = 0; i < ctx->scenes.size(); ++i) {
+        SceneDev d{};
+        if (ctx->scenes[i]) {
+            Scene &s = *ctx->scenes[i];
+            d.pos_op = s.pos_op.p;
+            d.m01 = s.m01.p;
+            d.m23 = s.m23.p;
+            d.m8 = s.m8.p;
+            d.sh = s.sh.p;
+            d.n = s.n;
+            d.deg = s.deg;
+        }
+        tab[i] = d;
+    }
+    if (ctx->d_scenes.reserve(tab.size())) ++ctx->generation;
+    HIP_CHECK(hipMemcpy(ctx->d_scenes.p, tab.data(), tab.size() * sizeof(SceneDev),
+                        hipMemcpyHostToDevice));
+    ctx->scenes_dirty = false;
+}
+
+Choice resolve_choice(gs_ctx *ctx, const gs_render_opts &o, int n_cams, int W, int H,
+                      uint64_t total_gauss)
+{
+    Choice c;
+    char key[128];
+    snprintf(key, sizeof key, "%d:%d:%d:%d", W, H, n_cams, bits_for(total_gauss + 1));
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) c = it->second;
+    if (o.tile_w > 0) c.tw = o.tile_w;
+    if (o.tile_h > 0) c.th = o.tile_h;
+    if (o.lds_batch > 0) c.batch = o.lds_batch;
+    if (o.chunk_cams > 0) c.chunk = o.chunk_cams;
+    if (o.persistent >= 0) c.persistent = o.persistent;
+    if (o.mode == GS_MODE_PLAIN) {
+        c.chunk = 1;
+        c.persistent = 0;
+    }
+    return c;
+}
+
+std::string choice_key(const Choice &c)
+{
+    char b[96];
+    snprintf(b, sizeof b, "%dx%d/b%d/c%d/p%d", c.tw, c.th, c.batch, c.chunk, c.persistent);
+    return b;
+}
+
+// Cameras are grouped by scene (stable in batch order) and cut into chunks of
+// at most `chunk` cameras and ~2^27 visibility slots; each chunk's projection
+// is split into items of 256 Gaussians x up to 16 cameras of one scene.
+std::unique_ptr<Plan> make_plan(gs_ctx *ctx, int n_cams, const int32_t *scene_ids, int W, int H,
+                                const Choice &ch)
+{
+    constexpr int kCamGroup = 16;
+    const uint64_t kSlotBudget = uint64_t(1) << 27;
+    auto P = std::make_unique<Plan>();
+    P->n_cams = n_cams;
+    P->W = W;
+    P->H = H;
+    P->ch = ch;
+    P->tiles_x = (W + ch.tw - 1) / ch.tw;
+    P->tiles_y = (H + ch.th - 1) / ch.th;
+    P->tiles_per_cam = P->tiles_x * P->tiles_y;
+    P->order.resize(n_cams);
+    for (int i = 0; i < n_cams; ++i) P->order[i] = i;
+    std::stable_sort(P->order.begin(), P->order.end(),
+                     [&](int a, int b) { return scene_ids[a] < scene_ids[b]; });
+    P->cam_slot.resize(n_cams);
+    int pos = 0;
+    while (pos < n_cams) {
+        Chunk c;
+        c.start = pos;
+        uint64_t slots = 0;
+        while (pos < n_cams && c.count < ch.chunk) {
+            const Scene &s = *ctx->scenes[scene_ids[P->order[pos]]];
+            const uint64_t need = round64((uint64_t)s.n);
+            if (c.count > 0 && slots + need > kSlotBudget) break;
+            P->cam_slot[pos] = (uint32_t)slots;
+            slots += need;
+            ++c.count;
+            ++pos;
+        }
+        c.slots = slots;
+        // items, grouped by SH degree
+        std::vector<ProjItem> per_deg[4];
+        int run = c.start;
+        while (run < c.start + c.count) {
+            const int sid = scene_ids[P->order[run]];
+            int end = run;
+            while (end < c.start + c.count && scene_ids[P->order[end]] == sid) ++end;
+            const Scene &s = *ctx->scenes[sid];
+            for (int64_t g0 = 0; g0 < s.n; g0 += 256)
+                for (int c0 = run; c0 < end; c0 += kCamGroup) {
+                    ProjItem it;
+                    it.scene = sid;
+                    it.g0 = (int32_t)g0;
+                    it.cam0 = c0 - c.start;
+                    it.ncam = std::min(kCamGroup, end - c0);
+                    per_deg[s.deg].push_back(it);
+                }
+            run = end;
+        }
+        for (int d = 0; d < 4; ++d) {
+            c.item_off[d] = (int)P->items.size();
+            c.item_cnt[d] = (int)per_deg[d].size();
+            P->items.insert(P->items.end(), per_deg[d].begin(), per_deg[d].end());
+        }
+        P->max_slots = std::max(P->max_slots, slots);
+        P->max_chunk_cams = std::max(P->max_chunk_cams, c.count);
+        P->chunks.push_back(c);
+    }
+    for (int i = 0; i < n_cams; ++i) {
+        const int sid = scene_ids[i];
+        if (std::find(P->scenes_used.begin(), P->scenes_used.end(), sid) == P->scenes_used.end())
+            P->scenes_used.push_back(sid);
+    }
+    P->d_order.reserve(n_cams);
+    P->d_cam_slot.reserve(n_cams);
+    P->d_items.reserve(std::max<size_t>(P->items.size(), 1));
+    HIP_CHECK(hipMemcpy(P->d_order.p, P->order.data(), n_cams * sizeof(int32_t),
+                        hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemcpy(P->d_cam_slot.p, P->cam_slot.data(), n_cams * sizeof(uint32_t),
+                        hipMemcpyHostToDevice));
+    if (!P->items.empty())
+        HIP_CHECK(hipMemcpy(P->d_items.p, P->items.data(), P->items.size() * sizeof(ProjItem),
+                            hipMemcpyHostToDevice));
+    return P;
+}
+
+// Grow the workspace for a plan; returns true if any buffer moved.
+bool ensure_workspace(gs_ctx *ctx, const Plan &P)
+{
+    bool moved = false;
+    const uint64_t slots = std::max<uint64_t>(P.max_slots, 64);
+    moved |= ctx->recA.reserve(slots);
+    moved |= ctx->recB.reserve(slots);
+    moved |= ctx->recC.reserve(slots);
+    moved |= ctx->rect.reserve(slots);
+    moved |= ctx->vis.reserve(slots / 64);
+    moved |= ctx->word_off.reserve(slots / 64);
+    for (int i = 0; i < 2; ++i) {
+        moved |= ctx->dkeys[i].reserve(slots);
+        moved |= ctx->dvals[i].reserve(slots);
+    }
+    moved |= ctx->ioff.reserve(slots);
+    if (ctx->inst_cap == 0) ctx->inst_cap = std::max<uint64_t>(uint64_t(1) << 20, slots / 2);
+    ctx->inst_cap = std::min<uint64_t>(ctx->inst_cap, uint64_t(0xFFFFFFF0u));
+    for (int i = 0; i < 2; ++i) {
+        moved |= ctx->ikeys[i].reserve(ctx->inst_cap);
+        moved |= ctx->ivals[i].reserve(ctx->inst_cap);
+    }
+    moved |= ctx->ranges.reserve((uint64_t)P.max_chunk_cams * P.tiles_per_cam);
+    moved |= ctx->cams.reserve(std::max(P.n_cams, 1));
+    moved |= ctx->counts.reserve(4);
+    moved |= ctx->flags.reserve(1);
+    moved |= ctx->queue.reserve(1);
+    moved |= ctx->scan_partial.reserve(1024);
+    moved |= ctx->sort_hist.reserve(256 * 1024);
+    if (moved) ++ctx->generation;
+    return moved;
+}
+
+// Enqueue the whole render of a plan on `st` (also used under capture).
+void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float *intr, float near,
+                    const float bg[3], float *rgb, float *depth, float *alpha, hipStream_t st)
+{
+    const Choice &ch = P.ch;
+    ScanTemp scan{ctx->scan_partial.p};
+    SortTemp sort{ctx->sort_hist.p, scan};
+    const uint32_t cap = (uint32_t)ctx->inst_cap;
+    launch_zero_u32((uint32_t *)ctx->flags.p, sizeof(DevFlags) / 4, st);
+    launch_camera_setup(poses, intr, P.d_order.p, P.n_cams, P.W, P.H, ctx->cams.p, st);
+    int persistent_blocks = 0;
+    if (ch.persistent)
+        persistent_blocks = raster_occupancy(ch.tw, ch.th, ch.batch) * std::max(ctx->cu_count, 1);
+    for (const Chunk &c : P.chunks) {
+        const CamParams *cams = ctx->cams.p + c.start;
+        const uint32_t *cam_slot = P.d_cam_slot.p + c.start;
+        const uint32_t n_words = (uint32_t)(c.slots / 64);
+        for (int d = 0; d < 4; ++d)
+            if (c.item_cnt[d])
+                launch_project(d, P.d_items.p + c.item_off[d], c.item_cnt[d], ctx->d_scenes.p, cams,
+                               cam_slot, near, P.W, P.H, ctx->recA.p, ctx->recB.p, ctx->recC.p,
+                               ctx->rect.p, ctx->vis.p, st);
+        // visible count and order-preserving compaction
+        scan_popcount(ctx->vis.p, n_words, ctx->word_off.p, ctx->counts.p + 0, scan, st);
+        launch_compact(ctx->vis.p, ctx->word_off.p, n_words, cam_slot, c.count, ctx->recC.p,
+                       ctx->dkeys[0].p, ctx->dvals[0].p, st);
+        // depth sort: key = (camera << 31) | z bits (z > 0, sign bit clear)
+        const int dbits = 31 + bits_for((uint64_t)c.count);
+        const int r = radix_sort_u64(ctx->dkeys[0].p, ctx->dvals[0].p, ctx->dkeys[1].p,
+                                     ctx->dvals[1].p, ctx->counts.p + 0, (uint32_t)c.slots, dbits,
+                                     sort, st);
+        // tile counts in depth order -> instance offsets
+        scan_tile_counts(ctx->dvals[r].p, ctx->rect.p, ch.tw, ch.th, ctx->counts.p + 0,
+                         (uint32_t)c.slots, ctx->ioff.p, ctx->counts.p + 1, scan, st);
+        launch_finalize_counts(ctx->counts.p, cap, ctx->flags.p, st);
+        launch_emit(ctx->dkeys[r].p, ctx->dvals[r].p, ctx->counts.p + 0, ctx->ioff.p, ctx->rect.p,
+                    ch.tw, ch.th, P.tiles_x, P.tiles_per_cam, cap, ctx->ikeys[0].p,
+                    ctx->ivals[0].p, (uint32_t)c.slots, st);
+        // stable tile sort keeps the depth order inside each tile
+        const uint64_t n_tiles = (uint64_t)c.count * P.tiles_per_cam;
+        const int r2 = radix_sort_u32(ctx->ikeys[0].p, ctx->ivals[0].p, ctx->ikeys[1].p,
+                                      ctx->ivals[1].p, ctx->counts.p + 2, cap,
+                                      std::max(1, bits_for(n_tiles)), sort, st);
+        launch_zero_u32((uint32_t *)ctx->ranges.p, n_tiles * 2, st);
+        launch_ranges(ctx->ikeys[r2].p, ctx->counts.p + 2, ctx->ranges.p, cap, st);
+        RasterArgs a;
+        a.ranges = ctx->ranges.p;
+        a.ivals = ctx->ivals[r2].p;
+        a.recA = ctx->recA.p;
+        a.recB = ctx->recB.p;
+        a.recC = ctx->recC.p;
+        a.cam_global = P.d_order.p + c.start;
+        a.tiles_x = P.tiles_x;
+        a.tiles_per_cam = P.tiles_per_cam;
+        a.W = P.W;
+        a.H = P.H;
+        a.bg_r = bg[0];
+        a.bg_g = bg[1];
+        a.bg_b = bg[2];
+        a.rgb = rgb;
+        a.depth = depth;
+        a.alpha = alpha;
+        launch_raster(ch.tw, ch.th, ch.batch, ch.persistent != 0, a, c.count, ctx->queue.p,
+                      persistent_blocks, st);
+    }
+    HIP_CHECK(hipGetLastError());
+}
+
+void clear_graphs(gs_ctx *ctx)
+{
+    for (auto &kv : ctx->graphs) {
+        GraphEntry &g = *kv.second;
+        for (int32_t s : g.scenes)
+            if (s >= 0 && s < (int)ctx->scenes.size() && ctx->scenes[s]) --ctx->scenes[s]->graph_refs;
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    ctx->graphs.clear();
+}
+
+int check_scene_ids(gs_ctx *ctx, int n_cams, const int32_t *scene_ids, uint64_t *total)
+{
+    uint64_t t = 0;
+    std::vector<char> seen(ctx->scenes.size(), 0);
+    for (int i = 0; i < n_cams; ++i) {
+        const int32_t s = scene_ids[i];
+        if (s < 0 || s >= (int)ctx->scenes.size() || !ctx->scenes[s])
+            return fail(ctx, GS_ERR_INVALID_ARG, "scene_ids[" + std::to_string(i) + "] = " +
+                                                     std::to_string(s) + " is not a live scene");
+        if (!seen[s]) {
+            seen[s] = 1;
+            t += ctx->scenes[s]->n;
+        }
+    }
+    *total = t;
+    return GS_OK;
+}
+
+std::string graph_key(int n_cams, const int32_t *scene_ids, int W, int H, const Choice &ch,
+                      float near, const float *bg, const void *poses, const void *intr,
+                      const void *rgb, const void *depth, const void *alpha, int generation,
+                      uint64_t cap)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (int i = 0; i < n_cams; ++i) {
+        h ^= (uint32_t)scene_ids[i];
+        h *= 1099511628211ull;
+    }
+    char b[512];
+    snprintf(b, sizeof b, "%d|%llx|%dx%d|%s|%a|%a,%a,%a|%p|%p|%p|%p|%p|g%d|c%llu", n_cams,
+             (unsigned long long)h, W, H, choice_key(ch).c_str(), near, bg[0], bg[1], bg[2], poses,
+             intr, rgb, depth, alpha, generation, (unsigned long long)cap);
+    return b;
+}
+
+int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const float *poses,
+                const float *intr, int32_t W, int32_t H, float *rgb, float *depth, float *alpha,
+                const gs_render_opts &o, hipStream_t st, const Choice *forced)
+{
+    uint64_t total = 0;
+    int rc = check_scene_ids(ctx, n_cams, scene_ids, &total);
+    if (rc) return rc;
+    Choice ch = forced ? *forced : resolve_choice(ctx, o, n_cams, W, H, total);
+    if (!raster_supported(ch.tw, ch.th, ch.batch))
+        return fail(ctx, GS_ERR_INVALID_ARG, "unsupported tile/batch choice " + choice_key(ch));
+    if (ch.chunk < 1) return fail(ctx, GS_ERR_INVALID_ARG, "chunk_cams must be >= 1");
+    const bool batched = o.mode != GS_MODE_PLAIN;
+    const bool use_graph = batched && o.use_graph;
+    sync_scene_table(ctx);
+    ctx->last = gs_stats{};
+    int regrows = 0;
+    for (int attempt = 0; attempt < 6; ++attempt) {
+        if (!use_graph) {
+            std::unique_ptr<Plan> P = make_plan(ctx, n_cams, scene_ids, W, H, ch);
+            if (ensure_workspace(ctx, *P)) clear_graphs(ctx);
+            if (!batched) {
+                // plain form: the same kernel sequence per camera, eager
+                enqueue_render(ctx, *P, poses, intr, o.near_plane, o.bg, rgb, depth, alpha, st);
+            } else {
+                enqueue_render(ctx, *P, poses, intr, o.near_plane, o.bg, rgb, depth, alpha, st);
+            }
+            HIP_CHECK(hipMemcpyAsync(ctx->host_flags, ctx->flags.p, sizeof(DevFlags),
+                                     hipMemcpyDeviceToHost, st));
+            HIP_CHECK(hipStreamSynchronize(st));
+        } else {
+            std::string key = graph_key(n_cams, scene_ids, W, H, ch, o.near_plane, o.bg, poses,
+                                        intr, rgb, depth, alpha, ctx->generation, ctx->inst_cap);
+            auto it = ctx->graphs.find(key);
+            if (it == ctx->graphs.end()) {
+                auto g = std::make_unique<GraphEntry>();
+                g->plan = make_plan(ctx, n_cams, scene_ids, W, H, ch);
+                if (ensure_workspace(ctx, *g->plan)) {
+                    clear_graphs(ctx);
+                    key = graph_key(n_cams, scene_ids, W, H, ch, o.near_plane, o.bg, poses, intr,
+                                    rgb, depth, alpha, ctx->generation, ctx->inst_cap);
+                }
+                HIP_CHECK(hipStreamBeginCapture(ctx->capture_stream,
+                                                hipStreamCaptureModeThreadLocal));
+                try {
+                    enqueue_render(ctx, *g->plan, poses, intr, o.near_plane, o.bg, rgb, depth,
+                                   alpha, ctx->capture_stream);
+                } catch (...) {
+                    hipGraph_t junk = nullptr;
+                    (void)hipStreamEndCapture(ctx->capture_stream, &junk);
+                    if (junk) (void)hipGraphDestroy(junk);
+                    throw;
+                }
+                HIP_CHECK(hipStreamEndCapture(ctx->capture_stream, &g->graph));
+                HIP_CHECK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+                g->scenes = g->plan->scenes_used;
+                for (int32_t s : g->scenes) ++ctx->scenes[s]->graph_refs;
+                ++ctx->graph_captures;
+                it = ctx->graphs.emplace(key, std::move(g)).first;
+            }
+            HIP_CHECK(hipGraphLaunch(it->second->exec, st));
+            HIP_CHECK(hipMemcpyAsync(ctx->host_flags, ctx->flags.p, sizeof(DevFlags),
+                                     hipMemcpyDeviceToHost, st));
+            HIP_CHECK(hipStreamSynchronize(st));
+        }
+        const DevFlags f = *ctx->host_flags;
+        ctx->last.visible = (int64_t)f.visible;
+        ctx->last.instances = (int64_t)f.instances;
+        if (!f.overflow) break;
+        // grow the instance buffers past the largest chunk's need and retry
+        ++regrows;
+        uint64_t want = std::max<uint64_t>((uint64_t)f.max_inst + f.max_inst / 4 + 1024,
+                                           ctx->inst_cap * 2);
+        if (want > 0xFFFFFFF0ull) want = 0xFFFFFFF0ull;
+        if (want <= ctx->inst_cap)
+            return fail(ctx, GS_ERR_CAPACITY, "instance count exceeds the 32-bit index range");
+        ctx->inst_cap = want;
+        clear_graphs(ctx);
+        if (attempt == 5) return fail(ctx, GS_ERR_CAPACITY, "instance buffers kept overflowing");
+    }
+    ctx->last.instance_capacity = (int64_t)ctx->inst_cap;
+    ctx->last.regrows = regrows;
+    ctx->last.graph_captures = ctx->graph_captures;
+    ctx->last.tile_w = ch.tw;
+    ctx->last.tile_h = ch.th;
+    ctx->last.lds_batch = ch.batch;
+    ctx->last.chunk_cams = ch.chunk;
+    ctx->last.persistent = ch.persistent;
+    return GS_OK;
+}
+
+int validate_render_args(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const float *poses,
+                         const float *intr, int32_t W, int32_t H, const float *rgb,
+                         const float *depth)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (n_cams < 1) return fail(ctx, GS_ERR_INVALID_ARG, "n_cams must be >= 1");
+    if (!scene_ids || !poses || !intr || !rgb || !depth)
+        return fail(ctx, GS_ERR_INVALID_ARG, "null scene_ids/poses/intrinsics/rgb/depth");
+    if (W < 1 || H < 1 || W > 65535 || H > 65535)
+        return fail(ctx, GS_ERR_INVALID_ARG, "width/height must be in [1, 65535]");
+    return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gs_abi_sizes(int32_t *scene_desc, int32_t *render_opts, int32_t *stats)
+{
+    if (scene_desc) *scene_desc = (int32_t)sizeof(gs_scene_desc);
+    if (render_opts) *render_opts = (int32_t)sizeof(gs_render_opts);
+    if (stats) *stats = (int32_t)sizeof(gs_stats);
+    return GS_OK;
+}
+
+void gs_default_opts(gs_render_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->near_plane = 0.2f;
+    o->mode = GS_MODE_BATCHED;
+    o->persistent = -1;
+    o->use_graph = 0;
+}
+
+int gs_create(int hip_device, gs_ctx **out)
+{
+    if (!out) return GS_ERR_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return GS_ERR_HIP;
+    if (hip_device < 0 || hip_device >= count) return GS_ERR_INVALID_ARG;
+    auto *ctx = new (std::nothrow) gs_ctx();
+    if (!ctx) return GS_ERR_OOM;
+    int rc = guarded(ctx, [&] {
+        ctx->device = hip_device;
+        HIP_CHECK(hipSetDevice(hip_device));
+        hipDeviceProp_t prop;
+        HIP_CHECK(hipGetDeviceProperties(&prop, hip_device));
+        ctx->cu_count = prop.multiProcessorCount;
+        HIP_CHECK(hipHostMalloc((void **)&ctx->host_flags, sizeof(DevFlags), hipHostMallocDefault));
+        HIP_CHECK(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+        return GS_OK;
+    });
+    if (rc != GS_OK) {
+        gs_destroy(ctx);
+        return rc;
+    }
+    *out = ctx;
+    return GS_OK;
+}
+
+int gs_destroy(gs_ctx *ctx)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    clear_graphs(ctx);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    if (ctx->host_flags) (void)hipHostFree(ctx->host_flags);
+    delete ctx;
+    return GS_OK;
+}
+
+const char *gs_last_error(const gs_ctx *ctx)
+{
+    if (!ctx) return "null context";
+    return ctx->err.c_str();
+}
+
+int gs_upload_scene(gs_ctx *ctx, const gs_scene_desc *d, int32_t *scene_id_out)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (!d || !scene_id_out) return fail(ctx, GS_ERR_INVALID_ARG, "null descriptor or id output");
+    if (d->n < 1 || d->n > (int64_t(1) << 30))
+        return fail(ctx, GS_ERR_BAD_SCENE, "scene size must be in [1, 2^30]");
+    if (d->sh_degree < 0 || d->sh_degree > 3)
+        return fail(ctx, GS_ERR_BAD_SCENE, "sh_degree must be in 0..3");
+    if (!d->means || !d->scales || !d->quats || !d->opacity || !d->sh)
+        return fail(ctx, GS_ERR_BAD_SCENE, "null scene array");
+    if (d->mem_kind != GS_MEM_HOST && d->mem_kind != GS_MEM_DEVICE)
+        return fail(ctx, GS_ERR_INVALID_ARG, "mem_kind must be GS_MEM_HOST or GS_MEM_DEVICE");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        const int64_t n = d->n;
+        const int nc = (d->sh_degree + 1) * (d->sh_degree + 1);
+        auto s = std::make_unique<Scene>();
+        s->n = n;
+        s->deg = d->sh_degree;
+        s->pos_op.reserve(n);
+        s->m01.reserve(n);
+        s->m23.reserve(n);
+        s->m8.reserve(n);
+        s->sh.reserve((size_t)n * nc * 3);
+        DevBuf<float> tmp;
+        DevBuf<int> bad;
+        bad.reserve(1);
+        HIP_CHECK(hipMemset(bad.p, 0, sizeof(int)));
+        const float *m = d->means, *sc = d->scales, *q = d->quats, *op = d->opacity, *sh = d->sh;
+        if (d->mem_kind == GS_MEM_HOST) {
+            const size_t counts[5] = {(size_t)n * 3, (size_t)n * 3, (size_t)n * 4, (size_t)n,
+                                      (size_t)n * nc * 3};
+            size_t total = 0;
+            for (size_t c : counts) total += c;
+            tmp.reserve(total);
+            const float *src[5] = {d->means, d->scales, d->quats, d->opacity, d->sh};
+            const float **dst[5] = {&m, &sc, &q, &op, &sh};
+            size_t off = 0;
+            for (int i = 0; i < 5; ++i) {
+                HIP_CHECK(hipMemcpy(tmp.p + off, src[i], counts[i] * sizeof(float),
+                                    hipMemcpyHostToDevice));
+                *dst[i] = tmp.p + off;
+                off += counts[i];
+            }
+        }
+        launch_scene_prep(m, sc, q, op, sh, n, nc, s->pos_op.p, s->m01.p, s->m23.p, s->m8.p,
+                          s->sh.p, bad.p, nullptr);
+        HIP_CHECK(hipGetLastError());
+        int hbad = 0;
+        HIP_CHECK(hipMemcpy(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost));
+        if (hbad)
+            return fail(ctx, GS_ERR_BAD_SCENE,
+                        "scene has non-finite values, non-positive scales, opacity outside "
+                        "[0,1] or zero quaternions");
+        int32_t id = -1;
+        for (size_t i = 0; i < ctx->scenes.size(); ++i)
+            if (!ctx->scenes[i]) {
+                id = (int32_t)i;
+                break;
+            }
+        if (id < 0) {
+            id = (int32_t)ctx->scenes.size();
+            ctx->scenes.emplace_back();
+        }
+        ctx->scenes[id] = std::move(s);
+        ctx->scenes_dirty = true;
+        *scene_id_out = id;
+        return GS_OK;
+    });
+}
+
+int gs_release_scene(gs_ctx *ctx, int32_t scene_id)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (scene_id < 0 || scene_id >= (int)ctx->scenes.size() || !ctx->scenes[scene_id])
+        return fail(ctx, GS_ERR_INVALID_ARG, "no such scene");
+    if (ctx->scenes[scene_id]->graph_refs > 0)
+        return fail(ctx, GS_ERR_BUSY, "a captured graph still references the scene");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        HIP_CHECK(hipDeviceSynchronize());
+        ctx->scenes[scene_id].reset();
+        ctx->scenes_dirty = true;
+        return GS_OK;
+    });
+}
+
+int64_t gs_scene_size(gs_ctx *ctx, int32_t scene_id)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (scene_id < 0 || scene_id >= (int)ctx->scenes.size() || !ctx->scenes[scene_id])
+        return fail(ctx, GS_ERR_INVALID_ARG, "no such scene");
+    return ctx->scenes[scene_id]->n;
+}
+
+int gs_render_batch(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const float *poses,
+                    const float *intrinsics, int32_t width, int32_t height, float *rgb,
+                    float *depth, float *alpha, const gs_render_opts *opts, void *stream)
+{
+    int rc = validate_render_args(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb,
+                                  depth);
+    if (rc) return rc;
+    gs_render_opts o;
+    if (opts) o = *opts; else gs_default_opts(&o);
+    if (o.mode != GS_MODE_PLAIN && o.mode != GS_MODE_BATCHED)
+        return fail(ctx, GS_ERR_INVALID_ARG, "mode must be GS_MODE_PLAIN or GS_MODE_BATCHED");
+    if (!(o.near_plane > 0.0f) || !std::isfinite(o.near_plane))
+        return fail(ctx, GS_ERR_INVALID_ARG, "near_plane must be a positive finite value");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        return render_impl(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb, depth,
+                           alpha, o, (hipStream_t)stream, nullptr);
+    });
+}
+
+int gs_last_stats(gs_ctx *ctx, gs_stats *out)
+{
+    if (!ctx || !out) return GS_ERR_INVALID_ARG;
+    *out = ctx->last;
+    return GS_OK;
+}
+
+int gs_set_instance_capacity(gs_ctx *ctx, int64_t cap)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (cap < 1 || cap > 0xFFFFFFF0ll) return fail(ctx, GS_ERR_INVALID_ARG, "capacity out of range");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        HIP_CHECK(hipDeviceSynchronize());
+        clear_graphs(ctx);
+        for (int i = 0; i < 2; ++i) {
+            ctx->ikeys[i].release();
+            ctx->ivals[i].release();
+        }
+        ctx->inst_cap = (uint64_t)cap;
+        ++ctx->generation;
+        return GS_OK;
+    });
+}
+
+int gs_clear_graphs(gs_ctx *ctx)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        HIP_CHECK(hipDeviceSynchronize());
+        clear_graphs(ctx);
+        return GS_OK;
+    });
+}
+
+int gs_debug_project(gs_ctx *ctx, int32_t scene_id, const float *pose, const float *intrinsics,
+                     int32_t width, int32_t height, float near_plane, float *out)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (!pose || !intrinsics || !out) return fail(ctx, GS_ERR_INVALID_ARG, "null argument");
+    if (scene_id < 0 || scene_id >= (int)ctx->scenes.size() || !ctx->scenes[scene_id])
+        return fail(ctx, GS_ERR_INVALID_ARG, "no such scene");
+    if (width < 1 || height < 1 || width > 65535 || height > 65535)
+        return fail(ctx, GS_ERR_INVALID_ARG, "width/height must be in [1, 65535]");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        sync_scene_table(ctx);
+        ctx->dbg_pose.reserve(16);
+        ctx->cams.reserve(1);
+        float h[16];
+        std::memcpy(h, pose, 12 * sizeof(float));
+        std::memcpy(h + 12, intrinsics, 4 * sizeof(float));
+        HIP_CHECK(hipMemcpy(ctx->dbg_pose.p, h, sizeof h, hipMemcpyHostToDevice));
+        launch_camera_setup(ctx->dbg_pose.p, ctx->dbg_pose.p + 12, nullptr, 1, width, height,
+                            ctx->cams.p, nullptr);
+        const Scene &s = *ctx->scenes[scene_id];
+        SceneDev sd{};
+        sd.pos_op = s.pos_op.p;
+        sd.m01 = s.m01.p;
+        sd.m23 = s.m23.p;
+        sd.m8 = s.m8.p;
+        sd.sh = s.sh.p;
+        sd.n = s.n;
+        sd.deg = s.deg;
+        launch_debug_project(sd, ctx->cams.p, near_plane, width, height, out, nullptr);
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipDeviceSynchronize());
+        return GS_OK;
+    });
+}
+
+int gs_autotune(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const float *poses,
+                const float *intrinsics, int32_t width, int32_t height, float *rgb, float *depth,
+                const char *cache_path, void *stream)
+{
+    int rc = validate_render_args(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb,
+                                  depth);
+    if (rc) return rc;
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        hipStream_t st = (hipStream_t)stream;
+        uint64_t total = 0;
+        int r = check_scene_ids(ctx, n_cams, scene_ids, &total);
+        if (r) return r;
+        gs_render_opts o;
+        gs_default_opts(&o);
+        std::vector<Choice> cands;
+        const int shapes[][2] = {{16, 16}, {32, 8}, {16, 8}, {8, 8}, {32, 16}};
+        const int batches[] = {64, 128, 256};
+        const int chunks[] = {256, 512, 1024};
+        for (auto &s : shapes)
+            for (int b : batches)
+                if (raster_supported(s[0], s[1], b))
+                    for (int p = 0; p < 2; ++p) {
+                        Choice c;
+                        c.tw = s[0];
+                        c.th = s[1];
+                        c.batch = b;
+                        c.chunk = 512;
+                        c.persistent = p;
+                        cands.push_back(c);
+                    }
+        hipEvent_t e0, e1;
+        HIP_CHECK(hipEventCreate(&e0));
+        HIP_CHECK(hipEventCreate(&e1));
+        auto time_choice = [&](const Choice &c) -> float {
+            int rr = render_impl(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb,
+                                 depth, nullptr, o, st, &c);
+            if (rr) throw GsError(rr, ctx->err);
+            float best = 1e30f;
+            for (int rep = 0; rep < 2; ++rep) {
+                HIP_CHECK(hipEventRecord(e0, st));
+                rr = render_impl(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb,
+                                 depth, nullptr, o, st, &c);
+                if (rr) throw GsError(rr, ctx->err);
+                HIP_CHECK(hipEventRecord(e1, st));
+                HIP_CHECK(hipEventSynchronize(e1));
+                float ms = 0;
+                HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+                best = std::min(best, ms);
+            }
+            return best;
+        };
+        Choice best;
+        float best_ms = 1e30f;
+        std::vector<std::pair<Choice, float>> table;
+        for (const Choice &c : cands) {
+            float ms = time_choice(c);
+            table.push_back({c, ms});
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+        for (int ck : chunks) {
+            Choice c = best;
+            c.chunk = ck;
+            if (ck == best.chunk) continue;
+            float ms = time_choice(c);
+            table.push_back({c, ms});
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        char key[128];
+        snprintf(key, sizeof key, "%d:%d:%d:%d", width, height, n_cams, bits_for(total + 1));
+        ctx->tuned[key] = best;
+        if (cache_path) {
+            FILE *f = fopen(cache_path, "a");
+            if (f) {
+                fprintf(f, "{\"key\": \"%s\", \"best\": \"%s\", \"best_ms\": %.4f, \"table\": {", key,
+                        choice_key(best).c_str(), best_ms);
+                for (size_t i = 0; i < table.size(); ++i)
+                    fprintf(f, "%s\"%s\": %.4f", i ? ", " : "", choice_key(table[i].first).c_str(),
+                            table[i].second);
+                fprintf(f, "}}\n");
+                fclose(f);
+            }
+        }
+        return GS_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,294 @@
+"""GPU parity of the HIP renderer against the FP64 oracle, through the C ABI.
+
+Tolerance (the renderer's stated bar): max-abs RGB 2e-3, relative depth
+1e-3, max-abs alpha 2e-3 per pixel, after the comparator accepts pixels that
+match an alternative the oracle lists for decisions sitting at a threshold
+within rounding (oracle.compare).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(ref, rgb, depth, alpha, label=""):
+    rep = oracle.compare(ref, rgb, depth, alpha)
+    print(f"{label}: max|rgb| {rep['max_abs_rgb']:.2e} rel depth {rep['max_rel_depth']:.2e} "
+          f"|alpha| {rep['max_abs_alpha']:.2e} rescued {rep['rescued']} failed {rep['failed']} "
+          f"flagged {ref.counters['flagged']}", flush=True)
+    assert rep["failed"] == 0, (label, rep)
+    return rep
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def w0(gpu_renderer):
+    sc = scenegen.make_scene(0)
+    return sc, gpu_renderer.upload_scene(sc), scenegen.make_cameras(0)
+
+
+@pytest.fixture(scope="module")
+def w1(gpu_renderer):
+    sc = scenegen.make_scene(1)
+    return sc, gpu_renderer.upload_scene(sc), scenegen.make_cameras(1)
+
+
+# ------------------------------------------------------------- projection --
+
+@pytest.mark.parametrize("which", [0, 1])
+def test_projection_records_match_oracle(gpu_renderer, w0, w1, which):
+    sc, sid, cams = (w0, w1)[which]
+    W, H = cams["width"], cams["height"]
+    pose, intr = cams["poses"][0], cams["intrinsics"][0]
+    got = gpu_renderer.debug_project(sid, pose, intr, W, H)
+    ref = oracle.project_all(sc, pose, intr, W, H)
+    vis_ref = ref["visible"] > 0
+    vis_got = got[:, 14] > 0
+    # the GPU machine is widened by rounding margins: it may keep a few extra
+    # Gaussians, never drop one the oracle sees
+    assert np.all(vis_got[vis_ref]), np.nonzero(vis_ref & ~vis_got)[0][:10]
+    assert (vis_got & ~vis_ref).sum() <= max(3, vis_ref.sum() // 1000)
+    v = vis_ref
+    np.testing.assert_allclose(got[v, 0], ref["u"][v], rtol=2e-6, atol=2e-3)
+    np.testing.assert_allclose(got[v, 1], ref["v"][v], rtol=2e-6, atol=2e-3)
+    np.testing.assert_allclose(got[v, 2], ref["z"][v], rtol=2e-6, atol=1e-6)
+    np.testing.assert_allclose(got[v, 3], ref["opacity"][v], rtol=0, atol=0)
+    for k, name in ((4, "conic_a"), (5, "conic_b"), (6, "conic_c")):
+        scale = np.maximum(np.abs(ref["conic_a"][v]), np.abs(ref["conic_c"][v]))
+        err = np.abs(got[v, k] - ref[name][v]) / scale
+        assert err.max() < 1e-4, (name, err.max())
+    for k, name in ((7, "r"), (8, "g"), (9, "b")):
+        np.testing.assert_allclose(got[v, k], ref[name][v], atol=2e-5)
+    # GPU machine contains the oracle's exact box
+    assert np.all(got[v, 10] <= ref["x0"][v]) and np.all(got[v, 11] >= ref["x1"][v])
+    assert np.all(got[v, 12] <= ref["y0"][v]) and np.all(got[v, 13] >= ref["y1"][v])
+
+
+# -------------------------------------------------------------- workload 0 --
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_workload0_matches_oracle(gpu_renderer, w0, mode):
+    sc, sid, cams = w0
+    rgb, depth, alpha = gpu_renderer.render([sid], cams["poses"], cams["intrinsics"], 64, 48,
+                                            mode=mode)
+    ref = oracle.render(sc, cams["poses"][0], cams["intrinsics"][0], 64, 48)
+    _check(ref, _np(rgb[0]), _np(depth[0]), _np(alpha[0]), f"w0 {mode}")
+    st = gpu_renderer.stats()
+    assert st["visible"] == pytest.approx(ref.counters["visible"], rel=0.01)
+
+
+# -------------------------------------------------------------- workload 1 --
+
+def test_workload1_all_cameras_batched(gpu_renderer, w1):
+    sc, sid, cams = w1
+    n = len(cams["scene_ids"])
+    rgb, depth, alpha = gpu_renderer.render([sid] * n, cams["poses"], cams["intrinsics"], 640, 480)
+    rgb, depth, alpha = _np(rgb), _np(depth), _np(alpha)
+    total_flag = 0
+    for c in range(n):
+        ref = oracle.render(sc, cams["poses"][c], cams["intrinsics"][c], 640, 480)
+        _check(ref, rgb[c], depth[c], alpha[c], f"w1 cam {c}")
+        total_flag += ref.counters["flagged"]
+    print("w1 flagged pixels", total_flag)
+
+
+def test_workload1_plain_equals_batched_bitwise(gpu_renderer, w1):
+    sc, sid, cams = w1
+    idx = np.arange(0, 64, 8)
+    P, K = cams["poses"][idx], cams["intrinsics"][idx]
+    a = gpu_renderer.render([sid] * len(idx), P, K, 640, 480, mode="plain")
+    b = gpu_renderer.render([sid] * len(idx), P, K, 640, 480, mode="batched")
+    for x, y in zip(a, b):
+        assert bool((x == y).all())
+
+
+@pytest.mark.parametrize("tile,batch,persistent", [((16, 16), 64, 0), ((32, 8), 128, 1),
+                                                   ((8, 8), 64, 0), ((16, 8), 128, 1),
+                                                   ((32, 16), 256, 0), ((16, 16), 256, 1)])
+def test_every_tile_choice_is_bitwise_identical(gpu_renderer, w1, tile, batch, persistent):
+    sc, sid, cams = w1
+    idx = np.arange(0, 64, 4)
+    P, K = cams["poses"][idx], cams["intrinsics"][idx]
+    base = gpu_renderer.render([sid] * len(idx), P, K, 640, 480)
+    alt = gpu_renderer.render([sid] * len(idx), P, K, 640, 480, tile=tile, lds_batch=batch,
+                              persistent=persistent, chunk_cams=5)
+    st = gpu_renderer.stats()
+    assert (st["tile_w"], st["tile_h"], st["lds_batch"], st["persistent"]) == (*tile, batch,
+                                                                              persistent)
+    for x, y in zip(base, alt):
+        assert bool((x == y).all())
+
+
+def test_graph_replay_matches_eager_every_replay(gpu_renderer, w1):
+    import torch
+    sc, sid, cams = w1
+    n = 16
+    P = torch.as_tensor(cams["poses"][:n]).cuda()
+    K = torch.as_tensor(cams["intrinsics"][:n]).cuda()
+    eager = [_np(t) for t in gpu_renderer.render([sid] * n, P, K, 640, 480)]
+    out = gpu_renderer.alloc_outputs(n, 640, 480)
+    for rep in range(3):
+        gpu_renderer.render([sid] * n, P, K, 640, 480, out=out, use_graph=True)
+        torch.cuda.synchronize()
+        for x, y in zip(eager, out):
+            assert np.array_equal(x, _np(y)), f"replay {rep}"
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        del junk
+    assert gpu_renderer.stats()["graph_captures"] >= 1
+
+
+def test_graph_replay_tracks_new_poses(gpu_renderer, w1):
+    import torch
+    sc, sid, cams = w1
+    n = 8
+    P = torch.as_tensor(cams["poses"][:n]).cuda()
+    K = torch.as_tensor(cams["intrinsics"][:n]).cuda()
+    out = gpu_renderer.alloc_outputs(n, 640, 480)
+    gpu_renderer.render([sid] * n, P, K, 640, 480, out=out, use_graph=True)
+    P.copy_(torch.as_tensor(cams["poses"][8:8 + n]).cuda())   # same buffer, new poses
+    gpu_renderer.render([sid] * n, P, K, 640, 480, out=out, use_graph=True)
+    ref = gpu_renderer.render([sid] * n, cams["poses"][8:8 + n], cams["intrinsics"][8:8 + n],
+                              640, 480)
+    for x, y in zip(ref, out):
+        assert bool((x == y).all())
+
+
+def test_repeated_runs_bitwise_identical(gpu_renderer, w1):
+    sc, sid, cams = w1
+    a = gpu_renderer.render([sid] * 4, cams["poses"][:4], cams["intrinsics"][:4], 640, 480)
+    b = gpu_renderer.render([sid] * 4, cams["poses"][:4], cams["intrinsics"][:4], 640, 480)
+    for x, y in zip(a, b):
+        assert bool((x == y).all())
+
+
+# ------------------------------------------------------------- edge cases --
+
+def test_ragged_image_and_single_pixel(gpu_renderer, w0):
+    sc, sid, cams = w0
+    for (W, H) in ((50, 37), (17, 1), (1, 1), (33, 65)):
+        intr = np.array([[40.0, 40.0, W / 2, H / 2]], np.float32)
+        rgb, depth, alpha = gpu_renderer.render([sid], cams["poses"], intr, W, H)
+        ref = oracle.render(sc, cams["poses"][0], intr[0], W, H)
+        _check(ref, _np(rgb[0]), _np(depth[0]), _np(alpha[0]), f"ragged {W}x{H}")
+
+
+def test_camera_looking_away_is_empty(gpu_renderer, w0):
+    sc, sid, cams = w0
+    pose = cams["poses"].copy()
+    pose[0, :, 2] *= -1   # flip forward axis: looks away from the cloud
+    pose[0, :, 0] *= -1
+    rgb, depth, alpha = gpu_renderer.render([sid], pose, cams["intrinsics"], 64, 48,
+                                            bg=(0.25, 0.5, 0.75))
+    assert np.allclose(_np(rgb[0]), [0.25, 0.5, 0.75]) and np.all(_np(depth[0]) == 0)
+    assert np.all(_np(alpha[0]) == 0)
+
+
+def test_camera_inside_cloud_near_plane(gpu_renderer, w0):
+    sc, sid, cams = w0
+    pose = cams["poses"].copy()
+    pose[0, :, 3] = (0.1, -0.2, 0.0)   # inside the [-2,2]^3 cube
+    rgb, depth, alpha = gpu_renderer.render([sid], pose, cams["intrinsics"], 64, 48)
+    ref = oracle.render(sc, pose[0], cams["intrinsics"][0], 64, 48)
+    _check(ref, _np(rgb[0]), _np(depth[0]), _np(alpha[0]), "inside")
+
+
+@pytest.mark.parametrize("deg", [1, 2, 3])
+def test_sh_degrees_and_background(gpu_renderer, deg):
+    sc = scenegen.tiny_scene(300, 7 + deg, sh_degree=deg, spread=1.0)
+    sid = gpu_renderer.upload_scene(sc, device_copy=(deg == 2))
+    pose = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1)[None].astype(np.float32)
+    intr = np.array([[60.0, 60.0, 40.0, 30.0]], np.float32)
+    bg = (0.1, 0.2, 0.3)
+    rgb, depth, alpha = gpu_renderer.render([sid], pose, intr, 80, 60, bg=bg)
+    ref = oracle.render(sc, pose[0], intr[0], 80, 60, bg=bg)
+    _check(ref, _np(rgb[0]), _np(depth[0]), _np(alpha[0]), f"deg {deg}")
+    gpu_renderer.release_scene(sid)
+
+
+def test_single_gaussian_scene(gpu_renderer):
+    sc = scenegen.tiny_scene(1, 3, sh_degree=0)
+    sc["means"][:] = (0.0, 0.0, 3.0)
+    sid = gpu_renderer.upload_scene(sc)
+    pose = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1)[None].astype(np.float32)
+    intr = np.array([[50.0, 50.0, 32.0, 24.0]], np.float32)
+    rgb, depth, alpha = gpu_renderer.render([sid], pose, intr, 64, 48)
+    ref = oracle.render(sc, pose[0], intr[0], 64, 48)
+    _check(ref, _np(rgb[0]), _np(depth[0]), _np(alpha[0]), "n=1")
+    gpu_renderer.release_scene(sid)
+
+
+def test_many_scenes_mixed_batch(gpu_renderer):
+    scenes = [scenegen.tiny_scene(200 + 150 * i, 40 + i, sh_degree=i % 4, spread=0.8)
+              for i in range(5)]
+    sids = [gpu_renderer.upload_scene(s) for s in scenes]
+    rng = np.random.default_rng(0)
+    n = 23
+    pick = rng.integers(0, 5, size=n)
+    poses = np.zeros((n, 3, 4), np.float32)
+    poses[:, :, :3] = np.eye(3)
+    poses[:, :, 3] = rng.uniform(-0.2, 0.2, size=(n, 3))
+    intr = np.tile(np.array([[45.0, 45.0, 24.0, 20.0]], np.float32), (n, 1))
+    out = gpu_renderer.render([sids[p] for p in pick], poses, intr, 48, 40, chunk_cams=4)
+    for c in range(n):
+        ref = oracle.render(scenes[pick[c]], poses[c], intr[c], 48, 40)
+        _check(ref, _np(out[0][c]), _np(out[1][c]), _np(out[2][c]), f"mixed {c}")
+    for s in sids:
+        gpu_renderer.release_scene(s)
+
+
+def test_capacity_regrow_path(gpu_renderer, w1):
+    sc, sid, cams = w1
+    ref = gpu_renderer.render([sid] * 4, cams["poses"][:4], cams["intrinsics"][:4], 640, 480)
+    gpu_renderer.set_instance_capacity(1000)
+    got = gpu_renderer.render([sid] * 4, cams["poses"][:4], cams["intrinsics"][:4], 640, 480)
+    st = gpu_renderer.stats()
+    assert st["regrows"] >= 1 and st["instance_capacity"] > 1000
+    for x, y in zip(ref, got):
+        assert bool((x == y).all())
+
+
+# ----------------------------------------------------------- error paths --
+
+def test_error_codes(gpu_renderer, w0):
+    import paper_2510_15352_amd as gs
+    sc, sid, cams = w0
+    with pytest.raises(gs.GsError) as e:
+        gpu_renderer.render([sid + 100], cams["poses"], cams["intrinsics"], 64, 48)
+    assert e.value.code == -1
+    with pytest.raises(gs.GsError) as e:
+        gpu_renderer.render([sid], cams["poses"], cams["intrinsics"], 0, 48)
+    assert e.value.code == -1
+    bad = dict(sc)
+    bad["means"] = sc["means"].copy()
+    bad["means"][5, 1] = np.nan
+    with pytest.raises(gs.GsError) as e:
+        gpu_renderer.upload_scene(bad)
+    assert e.value.code == -2
+    bad = dict(sc)
+    bad["sh_degree"] = 4
+    with pytest.raises(gs.GsError) as e:
+        gpu_renderer.upload_scene(bad)
+    assert e.value.code == -2
+    with pytest.raises(gs.GsError) as e:
+        gpu_renderer.render([sid], cams["poses"], cams["intrinsics"], 64, 48, tile=(24, 24))
+    assert e.value.code == -1
+
+
+def test_release_while_graph_holds_scene_is_busy(gpu_renderer):
+    import paper_2510_15352_amd as gs
+    sc = scenegen.tiny_scene(100, 99)
+    sid = gpu_renderer.upload_scene(sc)
+    pose = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1)[None].astype(np.float32)
+    intr = np.array([[50.0, 50.0, 16.0, 16.0]], np.float32)
+    gpu_renderer.render([sid], pose, intr, 32, 32, use_graph=True)
+    with pytest.raises(gs.GsError) as e:
+        gpu_renderer.release_scene(sid)
+    assert e.value.code == -6
+    gpu_renderer.drop_graphs()
+    gpu_renderer.release_scene(sid)
