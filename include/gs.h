@@ -83,8 +83,22 @@ typedef struct {
     int32_t chunk_cams;/* BATCHED: cameras per chunk; 0 = tuned/default */
     int32_t persistent;/* BATCHED: raster as a persistent work queue (1), a grid (0), -1 = tuned */
     int32_t use_graph; /* BATCHED: capture the step into a HIP graph and replay it (1) */
-    int32_t reserved[5];
+    int32_t timing;    /* record HIP events around every stage (eager renders only) */
+    int32_t count_pairs; /* also count contributing / evaluated (pixel, Gaussian) pairs
+                            with an instrumented raster kernel (slower; for measurement) */
+    int32_t reserved[3];
 } gs_render_opts;
+
+/* Stages timed when gs_render_opts.timing is set (indices of stage_ms). */
+#define GS_STAGE_SETUP 0   /* flag reset + camera setup */
+#define GS_STAGE_PROJECT 1 /* EWA projection + SH colour */
+#define GS_STAGE_COMPACT 2 /* visibility scan + compaction */
+#define GS_STAGE_DEPTH_SORT 3
+#define GS_STAGE_EMIT 4    /* tile-count scan + instance emission */
+#define GS_STAGE_TILE_SORT 5
+#define GS_STAGE_RANGES 6
+#define GS_STAGE_RASTER 7
+#define GS_N_STAGES 8
 
 typedef struct {
     int64_t visible;          /* (camera, Gaussian) pairs whose footprint meets the image */
@@ -93,7 +107,11 @@ typedef struct {
     int32_t regrows;          /* capacity regrowths during the last render */
     int32_t graph_captures;   /* graphs captured by this context so far */
     int32_t tile_w, tile_h, lds_batch, chunk_cams, persistent; /* choice actually used */
-    int32_t reserved;
+    int32_t stage_launches[GS_N_STAGES]; /* timed intervals per stage, one per camera chunk;
+                                            the raster stage is one kernel launch */
+    float stage_ms[GS_N_STAGES];         /* summed HIP-event time per stage (timing renders) */
+    int64_t pairs_contrib;   /* (pixel, Gaussian) pairs accumulated (count_pairs renders) */
+    int64_t pairs_evaluated; /* pairs whose alpha the raster evaluated (count_pairs renders) */
 } gs_stats;
 
 /* sizeof of gs_scene_desc, gs_render_opts and gs_stats as compiled into the

@@ -44,7 +44,10 @@ class RenderOpts(ctypes.Structure):
                 ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("lds_batch", ctypes.c_int32), ("chunk_cams", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("timing", ctypes.c_int32), ("count_pairs", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+STAGES = ("setup", "project", "compact", "depth_sort", "emit", "tile_sort", "ranges", "raster")
 
 
 class Stats(ctypes.Structure):
@@ -53,7 +56,8 @@ class Stats(ctypes.Structure):
                 ("graph_captures", ctypes.c_int32), ("tile_w", ctypes.c_int32),
                 ("tile_h", ctypes.c_int32), ("lds_batch", ctypes.c_int32),
                 ("chunk_cams", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("stage_launches", ctypes.c_int32 * 8), ("stage_ms", ctypes.c_float * 8),
+                ("pairs_contrib", ctypes.c_int64), ("pairs_evaluated", ctypes.c_int64)]
 
 
 _lib = None
@@ -171,7 +175,7 @@ class Renderer:
 
     # ------------------------------------------------------------ render --
     def opts(self, mode="batched", tile=None, lds_batch=0, chunk_cams=0, persistent=-1,
-             use_graph=False, near=0.2, bg=(0.0, 0.0, 0.0)):
+             use_graph=False, near=0.2, bg=(0.0, 0.0, 0.0), timing=False, count_pairs=False):
         o = RenderOpts()
         self.lib.gs_default_opts(ctypes.byref(o))
         o.mode = GS_MODE_PLAIN if mode == "plain" else GS_MODE_BATCHED
@@ -181,6 +185,8 @@ class Renderer:
         o.chunk_cams = int(chunk_cams)
         o.persistent = int(persistent)
         o.use_graph = int(bool(use_graph))
+        o.timing = int(bool(timing))
+        o.count_pairs = int(bool(count_pairs))
         o.near_plane = float(near)
         for i in range(3):
             o.bg[i] = float(bg[i])
@@ -219,7 +225,11 @@ class Renderer:
     def stats(self) -> dict:
         s = Stats()
         self._check(self.lib.gs_last_stats(self.ctx, ctypes.byref(s)))
-        return {k: getattr(s, k) for k, _ in Stats._fields_ if k != "reserved"}
+        out = {k: getattr(s, k) for k, _ in Stats._fields_
+               if k not in ("stage_ms", "stage_launches")}
+        out["stage_ms"] = dict(zip(STAGES, list(s.stage_ms)))
+        out["stage_launches"] = dict(zip(STAGES, list(s.stage_launches)))
+        return out
 
     def set_instance_capacity(self, cap: int):
         self._check(self.lib.gs_set_instance_capacity(self.ctx, int(cap)))

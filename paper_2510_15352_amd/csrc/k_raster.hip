@@ -71,9 +71,9 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ ike
 }
 
 // -------------------------------------------------------------- raster --
-template <int TW, int TH, int B>
+template <int TW, int TH, int B, bool COUNT = false>
 __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &a, float4 *sA,
-                                            float4 *sB, float2 *sC)
+                                            float4 *sB, float2 *sC, RenderFlags *cnt = nullptr)
 {
     constexpr int NT = TW * TH;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
@@ -85,6 +85,7 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
     Pixel s;
     s.T = 1.0f; s.r = 0.0f; s.g = 0.0f; s.b = 0.0f; s.zw = 0.0f;
     s.done = !inside;
+    uint32_t n_eval = 0, n_contrib = 0;
     for (uint32_t base = rg.x; base < rg.y; base += B) {
         const int cnt = (int)min((uint32_t)B, rg.y - base);
         __syncthreads();
@@ -98,11 +99,30 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
         __syncthreads();
         if (!s.done) {
             for (int j = 0; j < cnt; ++j) {
-                composite(s, px, py, sA[j], sB[j], sC[j]);
+                if (COUNT) {
+                    const float Tb = s.T;
+                    composite(s, px, py, sA[j], sB[j], sC[j]);
+                    ++n_eval;
+                    n_contrib += s.T != Tb;
+                } else {
+                    composite(s, px, py, sA[j], sB[j], sC[j]);
+                }
                 if (s.done) break;
             }
         }
         if (__syncthreads_count(!s.done) == 0) break;
+    }
+    if (COUNT) {
+        // one atomic per wave
+        uint64_t e = n_eval, c = n_contrib;
+        for (int d = 32; d > 0; d >>= 1) {
+            e += __shfl_down(e, d, 64);
+            c += __shfl_down(c, d, 64);
+        }
+        if (__lane_id() == 0) {
+            atomicAdd(&cnt->pairs_eval, (unsigned long long)e);
+            atomicAdd(&cnt->pairs_contrib, (unsigned long long)c);
+        }
     }
     if (inside) {
         const int64_t cg = a.cam_global[cl];
@@ -122,6 +142,16 @@ __global__ __launch_bounds__(TW *TH) void k_raster(RasterArgs a)
     __shared__ float4 sA[B], sB[B];
     __shared__ float2 sC[B];
     raster_tile<TW, TH, B>((int)blockIdx.y, (int)blockIdx.x, a, sA, sB, sC);
+}
+
+// Instrumented grid form: same per-pixel arithmetic, plus counts of
+// evaluated and accumulated (pixel, Gaussian) pairs.
+template <int TW, int TH, int B>
+__global__ __launch_bounds__(TW *TH) void k_raster_count(RasterArgs a, RenderFlags *cnt)
+{
+    __shared__ float4 sA[B], sB[B];
+    __shared__ float2 sC[B];
+    raster_tile<TW, TH, B, true>((int)blockIdx.y, (int)blockIdx.x, a, sA, sB, sC, cnt);
 }
 
 // Persistent form: a grid sized to the resident capacity pulls
@@ -207,13 +237,16 @@ int raster_occupancy(int tw, int th, int b)
 }
 
 void launch_raster(int tw, int th, int b, bool persistent, const RasterArgs &a, int n_cams,
-                   uint32_t *queue, int persistent_blocks, hipStream_t st)
+                   uint32_t *queue, int persistent_blocks, RenderFlags *count, hipStream_t st)
 {
     const int tiles = a.tiles_per_cam;
     const uint32_t n_items = (uint32_t)tiles * (uint32_t)n_cams;
 #define X(TW_, TH_, B_)                                                                          \
     if (tw == TW_ && th == TH_ && b == B_) {                                                     \
-        if (persistent) {                                                                        \
+        if (count) {                                                                             \
+            hipLaunchKernelGGL((k_raster_count<TW_, TH_, B_>), dim3(tiles, n_cams),             \
+                               dim3(TW_ * TH_), 0, st, a, count);                                \
+        } else if (persistent) {                                                                 \
             launch_zero_u32(queue, 1, st);                                                       \
             int blocks = persistent_blocks;                                                      \
             if ((uint32_t)blocks > n_items) blocks = (int)n_items;                               \

@@ -17,6 +17,8 @@ struct RenderFlags {
     uint32_t max_inst;
     unsigned long long visible;
     unsigned long long instances;
+    unsigned long long pairs_contrib;  // filled by the counting raster only
+    unsigned long long pairs_eval;
 };
 
 struct ScanTemp {
@@ -77,7 +79,8 @@ void launch_ranges(const uint32_t *ikeys, const uint32_t *n_dev, uint2 *ranges, 
                    hipStream_t st);
 bool raster_supported(int tw, int th, int b);
 int raster_occupancy(int tw, int th, int b);
+// count != nullptr selects the instrumented (pair-counting) grid kernel.
 void launch_raster(int tw, int th, int b, bool persistent, const RasterArgs &a, int n_cams,
-                   uint32_t *queue, int persistent_blocks, hipStream_t st);
+                   uint32_t *queue, int persistent_blocks, RenderFlags *count, hipStream_t st);
 
 }  // namespace gs

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -135,6 +136,7 @@ struct gs_ctx {
     DevFlags *host_flags = nullptr;  // pinned
     hipStream_t capture_stream = nullptr;
 
+    std::vector<hipEvent_t> events;  // pool for stage timing
     std::map<std::string, std::unique_ptr<GraphEntry>> graphs;
     std::map<std::string, Choice> tuned;
     gs_stats last{};
@@ -340,16 +342,54 @@ bool ensure_workspace(gs_ctx *ctx, const Plan &P)
     return moved;
 }
 
+// HIP events around each stage of an eager render.
+struct StageTimer {
+    gs_ctx *ctx;
+    hipStream_t st;
+    bool on;
+    size_t used = 0;
+    std::vector<std::array<size_t, 3>> marks;  // stage, begin event, end event
+    size_t record()
+    {
+        if (used == ctx->events.size()) {
+            hipEvent_t e;
+            HIP_CHECK(hipEventCreate(&e));
+            ctx->events.push_back(e);
+        }
+        HIP_CHECK(hipEventRecord(ctx->events[used], st));
+        return used++;
+    }
+    size_t begin() { return on ? record() : 0; }
+    void end(int stage, size_t b)
+    {
+        if (on) marks.push_back({(size_t)stage, b, record()});
+    }
+    void collect(gs_stats &s)
+    {
+        for (auto &m : marks) {
+            float ms = 0.0f;
+            HIP_CHECK(hipEventElapsedTime(&ms, ctx->events[m[1]], ctx->events[m[2]]));
+            s.stage_ms[m[0]] += ms;
+            s.stage_launches[m[0]] += 1;
+        }
+    }
+};
+
 // Enqueue the whole render of a plan on `st` (also used under capture).
 void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float *intr, float near,
-                    const float bg[3], float *rgb, float *depth, float *alpha, hipStream_t st)
+                    const float bg[3], float *rgb, float *depth, float *alpha, hipStream_t st,
+                    StageTimer *tm = nullptr, bool count_pairs = false)
 {
+    StageTimer off{ctx, st, false};
+    StageTimer &T = tm ? *tm : off;
     const Choice &ch = P.ch;
     ScanTemp scan{ctx->scan_partial.p};
     SortTemp sort{ctx->sort_hist.p, scan};
     const uint32_t cap = (uint32_t)ctx->inst_cap;
+    size_t t0 = T.begin();
     launch_zero_u32((uint32_t *)ctx->flags.p, sizeof(DevFlags) / 4, st);
     launch_camera_setup(poses, intr, P.d_order.p, P.n_cams, P.W, P.H, ctx->cams.p, st);
+    T.end(GS_STAGE_SETUP, t0);
     int persistent_blocks = 0;
     if (ch.persistent)
         persistent_blocks = raster_occupancy(ch.tw, ch.th, ch.batch) * std::max(ctx->cu_count, 1);
@@ -357,34 +397,46 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
         const CamParams *cams = ctx->cams.p + c.start;
         const uint32_t *cam_slot = P.d_cam_slot.p + c.start;
         const uint32_t n_words = (uint32_t)(c.slots / 64);
+        t0 = T.begin();
         for (int d = 0; d < 4; ++d)
             if (c.item_cnt[d])
                 launch_project(d, P.d_items.p + c.item_off[d], c.item_cnt[d], ctx->d_scenes.p, cams,
                                cam_slot, near, P.W, P.H, ctx->recA.p, ctx->recB.p, ctx->recC.p,
                                ctx->rect.p, ctx->vis.p, st);
+        T.end(GS_STAGE_PROJECT, t0);
         // visible count and order-preserving compaction
+        t0 = T.begin();
         scan_popcount(ctx->vis.p, n_words, ctx->word_off.p, ctx->counts.p + 0, scan, st);
         launch_compact(ctx->vis.p, ctx->word_off.p, n_words, cam_slot, c.count, ctx->recC.p,
                        ctx->dkeys[0].p, ctx->dvals[0].p, st);
+        T.end(GS_STAGE_COMPACT, t0);
         // depth sort: key = (camera << 31) | z bits (z > 0, sign bit clear)
         const int dbits = 31 + bits_for((uint64_t)c.count);
+        t0 = T.begin();
         const int r = radix_sort_u64(ctx->dkeys[0].p, ctx->dvals[0].p, ctx->dkeys[1].p,
                                      ctx->dvals[1].p, ctx->counts.p + 0, (uint32_t)c.slots, dbits,
                                      sort, st);
+        T.end(GS_STAGE_DEPTH_SORT, t0);
         // tile counts in depth order -> instance offsets
+        t0 = T.begin();
         scan_tile_counts(ctx->dvals[r].p, ctx->rect.p, ch.tw, ch.th, ctx->counts.p + 0,
                          (uint32_t)c.slots, ctx->ioff.p, ctx->counts.p + 1, scan, st);
         launch_finalize_counts(ctx->counts.p, cap, ctx->flags.p, st);
         launch_emit(ctx->dkeys[r].p, ctx->dvals[r].p, ctx->counts.p + 0, ctx->ioff.p, ctx->rect.p,
                     ch.tw, ch.th, P.tiles_x, P.tiles_per_cam, cap, ctx->ikeys[0].p,
                     ctx->ivals[0].p, (uint32_t)c.slots, st);
+        T.end(GS_STAGE_EMIT, t0);
         // stable tile sort keeps the depth order inside each tile
         const uint64_t n_tiles = (uint64_t)c.count * P.tiles_per_cam;
+        t0 = T.begin();
         const int r2 = radix_sort_u32(ctx->ikeys[0].p, ctx->ivals[0].p, ctx->ikeys[1].p,
                                       ctx->ivals[1].p, ctx->counts.p + 2, cap,
                                       std::max(1, bits_for(n_tiles)), sort, st);
+        T.end(GS_STAGE_TILE_SORT, t0);
+        t0 = T.begin();
         launch_zero_u32((uint32_t *)ctx->ranges.p, n_tiles * 2, st);
         launch_ranges(ctx->ikeys[r2].p, ctx->counts.p + 2, ctx->ranges.p, cap, st);
+        T.end(GS_STAGE_RANGES, t0);
         RasterArgs a;
         a.ranges = ctx->ranges.p;
         a.ivals = ctx->ivals[r2].p;
@@ -402,8 +454,10 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
         a.rgb = rgb;
         a.depth = depth;
         a.alpha = alpha;
+        t0 = T.begin();
         launch_raster(ch.tw, ch.th, ch.batch, ch.persistent != 0, a, c.count, ctx->queue.p,
-                      persistent_blocks, st);
+                      persistent_blocks, count_pairs ? ctx->flags.p : nullptr, st);
+        T.end(GS_STAGE_RASTER, t0);
     }
     HIP_CHECK(hipGetLastError());
 }
@@ -472,15 +526,13 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
     ctx->last = gs_stats{};
     int regrows = 0;
     for (int attempt = 0; attempt < 6; ++attempt) {
+        StageTimer timer{ctx, st, o.timing != 0};
         if (!use_graph) {
+            // eager: the plain form is the same kernel sequence with one camera per chunk
             std::unique_ptr<Plan> P = make_plan(ctx, n_cams, scene_ids, W, H, ch);
             if (ensure_workspace(ctx, *P)) clear_graphs(ctx);
-            if (!batched) {
-                // plain form: the same kernel sequence per camera, eager
-                enqueue_render(ctx, *P, poses, intr, o.near_plane, o.bg, rgb, depth, alpha, st);
-            } else {
-                enqueue_render(ctx, *P, poses, intr, o.near_plane, o.bg, rgb, depth, alpha, st);
-            }
+            enqueue_render(ctx, *P, poses, intr, o.near_plane, o.bg, rgb, depth, alpha, st, &timer,
+                           o.count_pairs != 0);
             HIP_CHECK(hipMemcpyAsync(ctx->host_flags, ctx->flags.p, sizeof(DevFlags),
                                      hipMemcpyDeviceToHost, st));
             HIP_CHECK(hipStreamSynchronize(st));
@@ -520,8 +572,12 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
             HIP_CHECK(hipStreamSynchronize(st));
         }
         const DevFlags f = *ctx->host_flags;
+        ctx->last = gs_stats{};
         ctx->last.visible = (int64_t)f.visible;
         ctx->last.instances = (int64_t)f.instances;
+        ctx->last.pairs_contrib = (int64_t)f.pairs_contrib;
+        ctx->last.pairs_evaluated = (int64_t)f.pairs_eval;
+        timer.collect(ctx->last);
         if (!f.overflow) break;
         // grow the instance buffers past the largest chunk's need and retry
         ++regrows;
@@ -613,6 +669,7 @@ int gs_destroy(gs_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     clear_graphs(ctx);
+    for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     if (ctx->host_flags) (void)hipHostFree(ctx->host_flags);
     delete ctx;
