@@ -31,7 +31,8 @@ struct CamParams {
     float C[3];    // camera centre in the world frame
     float fx, fy, cx, cy;
     float lxn, lxp, lyn, lyp;  // clamped tangent range of x/z and y/z
-    float pad[9];
+    float kx, ky;              // sqrt(1 + max clamped tangent^2): bounds |row of J| z / f
+    float pad[7];
 };
 static_assert(sizeof(CamParams) == 32 * 4, "CamParams is 128 B");
 
@@ -40,7 +41,8 @@ struct SceneDev {
     const float4 *pos_op;  // [n] (mx, my, mz, opacity)
     const float4 *m01;     // [n] M = R(q) S row-major: (m00, m01, m02, m10)
     const float4 *m23;     // [n] (m11, m12, m20, m21)
-    const float *m8;       // [n] m22
+    const float2 *m8r;     // [n] (m22, rad): rad = sqrt(2 ln(255 o)) * largest scale, the
+                           // radius of the alpha >= 1/255 region (0 when o < 1/255)
     const float *sh;       // [(deg+1)^2 * 3][n] planar
     int64_t n;
     int32_t deg;
@@ -59,11 +61,15 @@ struct ProjItem {
 // Raster-ready record of a visible (camera, Gaussian) pair, 48 bytes:
 //   A = (u, v, e_x, e_y)   with  e = e_x dx + e_y dy
 //   B = (f_y, opacity, r, g)     f = f_y dy
-//   C = (b, z, 0, 0)
-// so that alpha = min(0.99, o * 2^-(e^2 + f^2)) at offset (dx, dy).
+//   C = (b, z, tau, 0)
+// so that alpha = min(0.99, o * 2^-q), q = e^2 + f^2, at offset (dx, dy).
 // (e, f) is the upper-triangular factor U of the conic, U^T U = Sigma'^-1,
 // scaled by sqrt(log2(e)/2): a sum of squares, free of the cancellation of
 // the expanded quadratic form for thin, magnified Gaussians.
+// tau bounds q from above wherever alpha can reach 1/255 (log2(255 o) plus
+// a rounding margin): a pixel rectangle whose smallest q exceeds tau cannot
+// receive anything from the Gaussian. The binning record `rect` is the
+// inclusive pixel box (x0 | x1 << 16, y0 | y1 << 16).
 
 __device__ __forceinline__ uint64_t lanemask_lt()
 {
@@ -141,13 +147,67 @@ struct Projected {
     int x0, x1, y0, y1;  // inclusive pixel-centre box
 };
 
+// Smallest q(dx, dy) = (a dx + b dy)^2 + (c dy)^2 (a, c > 0) over the
+// rectangle [X0, X1] x [Y0, Y1]: 0 if it holds the origin, otherwise the
+// smallest of the four edge minima (1D quadratics, minimiser clamped to the
+// edge). Evaluating q at a point of the edge can only over-estimate the
+// edge minimum by the (second-order) error of the minimiser.
+__device__ __forceinline__ float rect_min_q(float a, float b, float c, float X0, float X1, float Y0,
+                                            float Y1)
+{
+    if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return 0.0f;
+    const float ia = __builtin_amdgcn_rcpf(a);
+    const float kv = a * b * __builtin_amdgcn_rcpf(fmaf(b, b, c * c));
+    float best;
+    {
+        const float dx0 = fminf(fmaxf(-b * Y0 * ia, X0), X1);
+        const float e0 = fmaf(a, dx0, b * Y0), f0 = c * Y0;
+        const float dx1 = fminf(fmaxf(-b * Y1 * ia, X0), X1);
+        const float e1 = fmaf(a, dx1, b * Y1), f1 = c * Y1;
+        best = fminf(fmaf(e0, e0, f0 * f0), fmaf(e1, e1, f1 * f1));
+    }
+    {
+        const float dy0 = fminf(fmaxf(-kv * X0, Y0), Y1);
+        const float e0 = fmaf(a, X0, b * dy0), f0 = c * dy0;
+        const float dy1 = fminf(fmaxf(-kv * X1, Y0), Y1);
+        const float e1 = fmaf(a, X1, b * dy1), f1 = c * dy1;
+        best = fminf(best, fminf(fmaf(e0, e0, f0 * f0), fmaf(e1, e1, f1 * f1)));
+    }
+    return best;
+}
+
+// Tiles of the footprint box: key = first + ty * tiles_x + tx.
+struct TileBox {
+    int tx0, ty0, bw, bh;
+};
+
+__device__ __forceinline__ TileBox tile_box(uint2 r, int tw, int th)
+{
+    TileBox b;
+    b.tx0 = (int)(r.x & 0xffffu) / tw;
+    b.ty0 = (int)(r.y & 0xffffu) / th;
+    b.bw = (int)(r.x >> 16) / tw - b.tx0 + 1;
+    b.bh = (int)(r.y >> 16) / th - b.ty0 + 1;
+    return b;
+}
+
+// Can the Gaussian (A, f_y, tau) reach alpha >= 1/255 at some pixel centre
+// of the pixel rectangle [px0, px1] x [py0, py1] (inclusive indices)?
+__device__ __forceinline__ bool may_touch(float4 A, float fy, float tau, int px0, int px1, int py0,
+                                          int py1)
+{
+    const float X0 = (float)px0 + 0.5f - A.x, X1 = (float)px1 + 0.5f - A.x;
+    const float Y0 = (float)py0 + 0.5f - A.y, Y1 = (float)py1 + 0.5f - A.y;
+    return rect_min_q(A.z, A.w, fy, X0, X1, Y0, Y1) <= tau;
+}
+
 // EWA projection of one Gaussian into one camera (steps: cull at the near
 // plane; T = J W; Sigma' = T M M^T T^T + 0.3 I with M = R(q) S; conic
 // factor; exact footprint box of alpha >= 1/255). Returns false when the
 // Gaussian is behind the near plane, too transparent or off-image.
 // Colour is filled by the caller (it needs the SH coefficients).
 __device__ __forceinline__ bool project_gaussian(const CamParams &cam, float4 pos_op, float4 m01,
-                                                 float4 m23, float m22, float near, int W, int H,
+                                                 float4 m23, float2 m8r, float near, int W, int H,
                                                  Projected &P)
 {
     const float mx = pos_op.x, my = pos_op.y, mz = pos_op.z, o = pos_op.w;
@@ -155,6 +215,18 @@ __device__ __forceinline__ bool project_gaussian(const CamParams &cam, float4 po
     const float y = fmaf(cam.R[3], mx, fmaf(cam.R[4], my, fmaf(cam.R[5], mz, cam.t[1])));
     const float z = fmaf(cam.R[6], mx, fmaf(cam.R[7], my, fmaf(cam.R[8], mz, cam.t[2])));
     if (!(z > near) || !(o >= kAlphaMin)) return false;
+    {
+        // Conservative screen test before the full projection. The exact box
+        // half-width is sqrt(2 ln(255 o) Sigma'_xx) with Sigma'_xx <=
+        // |J row|^2 (largest scale)^2 + 0.3 and sqrt(2 ln 255 * 0.3) < 1.83;
+        // 1% and one pixel of slack cover the approximate reciprocal.
+        const float rz = __builtin_amdgcn_rcpf(z);
+        const float ub = fmaf(cam.fx * x, rz, cam.cx), vb = fmaf(cam.fy * y, rz, cam.cy);
+        const float ex = fmaf(1.01f * m8r.y * rz, cam.fx * cam.kx, 2.84f);
+        const float ey = fmaf(1.01f * m8r.y * rz, cam.fy * cam.ky, 2.84f);
+        if (ub + ex < 0.0f || ub - ex > (float)W || vb + ey < 0.0f || vb - ey > (float)H)
+            return false;
+    }
     const float iz = 1.0f / z;
     const float xz = x * iz, yz = y * iz;
     const float u = fmaf(cam.fx, xz, cam.cx);
@@ -172,7 +244,7 @@ __device__ __forceinline__ bool project_gaussian(const CamParams &cam, float4 po
     const float t12 = fmaf(j12, cam.R[8], j11 * cam.R[5]);
     // M = R(q) S, row-major m[3][3]
     const float M00 = m01.x, M01 = m01.y, M02 = m01.z, M10 = m01.w;
-    const float M11 = m23.x, M12 = m23.y, M20 = m23.z, M21 = m23.w, M22 = m22;
+    const float M11 = m23.x, M12 = m23.y, M20 = m23.z, M21 = m23.w, M22 = m8r.x;
     // p = T_0 M, q = T_1 M  (so Sigma'_0 = [[p.p, p.q], [p.q, q.q]])
     const float p0 = fmaf(t00, M00, fmaf(t01, M10, t02 * M20));
     const float p1 = fmaf(t00, M01, fmaf(t01, M11, t02 * M21));
@@ -213,7 +285,9 @@ __device__ __forceinline__ bool project_gaussian(const CamParams &cam, float4 po
     P.y1 = (int)fminf(fy1, (float)(H - 1));
     P.A = make_float4(u, v, ex * kHalfLog2e_sqrt, ey * kHalfLog2e_sqrt);
     P.B = make_float4(fy * kHalfLog2e_sqrt, o, 0.0f, 0.0f);
-    P.C = make_float4(0.0f, z, 0.0f, 0.0f);
+    // alpha >= 1/255 needs q <= log2(255 o); margin for FP32 rounding
+    const float tau = fmaf(log2f(o * 255.0f), 1.001f, 0.002f);
+    P.C = make_float4(0.0f, z, tau, 0.0f);
     return true;
 }
 
@@ -228,7 +302,7 @@ struct Pixel {
 // new transmittance would fall under 1e-4; otherwise weight alpha T is
 // accumulated into colour and depth.
 __device__ __forceinline__ void composite(Pixel &s, float px, float py, float4 A, float4 B,
-                                          float2 C)
+                                          float4 C)
 {
     const float dx = px - A.x, dy = py - A.y;
     const float e = fmaf(A.w, dy, A.z * dx);

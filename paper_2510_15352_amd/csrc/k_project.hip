@@ -6,15 +6,16 @@
 namespace gs {
 
 // ------------------------------------------------------------ scene prep --
-// M = R(q/|q|) diag(scale); SH re-laid out planar [(k*3 + c)][n] so that a
-// wave reading one coefficient of 64 Gaussians is one coalesced 256 B load.
+// M = R(q/|q|) diag(scale); rad = sqrt(2 ln(255 o)) * largest scale; SH
+// re-laid out planar [(k*3 + c)][n] so that a wave reading one coefficient
+// of 64 Gaussians is one coalesced 256 B load.
 // bad[0] is set when a value is non-finite, a scale is not positive, an
 // opacity leaves [0, 1] or a quaternion is zero.
 __global__ void k_scene_prep(const float *__restrict__ means, const float *__restrict__ scales,
                              const float *__restrict__ quats, const float *__restrict__ opacity,
                              const float *__restrict__ sh, int64_t n, int ncoef,
                              float4 *__restrict__ pos_op, float4 *__restrict__ m01,
-                             float4 *__restrict__ m23, float *__restrict__ m8,
+                             float4 *__restrict__ m23, float2 *__restrict__ m8r,
                              float *__restrict__ sh_planar, int *__restrict__ bad)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -38,7 +39,9 @@ __global__ void k_scene_prep(const float *__restrict__ means, const float *__res
     pos_op[g] = make_float4(mx, my, mz, o);
     m01[g] = make_float4(R00 * sx, R01 * sy, R02 * sz, R10 * sx);
     m23[g] = make_float4(R11 * sy, R12 * sz, R20 * sx, R21 * sy);
-    m8[g] = R22 * sz;
+    const float smax = fmaxf(sx, fmaxf(sy, sz));
+    const float r2 = 2.0f * logf(o * 255.0f);
+    m8r[g] = make_float2(R22 * sz, o >= kAlphaMin ? sqrtf(fmaxf(r2, 0.0f)) * smax : 0.0f);
     for (int k = 0; k < ncoef * 3; ++k) {
         const float c = sh[g * ncoef * 3 + k];
         ok = ok && isfinite(c);
@@ -71,7 +74,9 @@ __global__ void k_camera_setup(const float *__restrict__ poses, const float *__r
     c.lxp = kTanClamp * ((float)W - c.cx) / c.fx;
     c.lyn = -kTanClamp * c.cy / c.fy;
     c.lyp = kTanClamp * ((float)H - c.cy) / c.fy;
-    for (int k = 0; k < 9; ++k) c.pad[k] = 0.0f;
+    c.kx = sqrtf(1.0f + fmaxf(c.lxn * c.lxn, c.lxp * c.lxp));
+    c.ky = sqrtf(1.0f + fmaxf(c.lyn * c.lyn, c.lyp * c.lyp));
+    for (int k = 0; k < 7; ++k) c.pad[k] = 0.0f;
     out[cl] = c;
 }
 
@@ -87,35 +92,46 @@ __global__ __launch_bounds__(256) void k_project(
     const ProjItem *__restrict__ items, const SceneDev *__restrict__ scenes,
     const CamParams *__restrict__ cams, const uint32_t *__restrict__ cam_slot,
     float near, int W, int H, float4 *__restrict__ recA, float4 *__restrict__ recB,
-    float4 *__restrict__ recC, uint2 *__restrict__ rect, uint64_t *__restrict__ vis)
+    float4 *__restrict__ recC, uint2 *__restrict__ rect, uint32_t *__restrict__ zbits,
+    uint64_t *__restrict__ vis)
 {
     constexpr int NC = (DEG + 1) * (DEG + 1);
+    constexpr int kMaxCams = 16;
+    __shared__ CamParams s_cam[kMaxCams];
+    __shared__ uint32_t s_slot[kMaxCams];
     const ProjItem it = items[blockIdx.x];
+    {
+        // the item's camera constants, staged once per block
+        float *dst = reinterpret_cast<float *>(s_cam);
+        const float *src = reinterpret_cast<const float *>(cams + it.cam0);
+        for (int j = (int)threadIdx.x; j < it.ncam * 32; j += 256) dst[j] = src[j];
+        if ((int)threadIdx.x < it.ncam) s_slot[threadIdx.x] = cam_slot[it.cam0 + threadIdx.x];
+    }
     const SceneDev sc = scenes[it.scene];
     const int g = it.g0 + (int)threadIdx.x;
     const bool in_range = g < sc.n;
     const int wave_g0 = it.g0 + (int)(threadIdx.x & ~63u);
     const bool wave_live = wave_g0 < sc.n;  // this wave owns a visibility word
     float4 po = make_float4(0.f, 0.f, 0.f, 0.f), a = po, b = po;
-    float m8 = 0.0f;
+    float2 m8r = make_float2(0.f, 0.f);
     float k[NC * 3];
     if (in_range) {
         po = sc.pos_op[g];
         a = sc.m01[g];
         b = sc.m23[g];
-        m8 = sc.m8[g];
+        m8r = sc.m8r[g];
 #pragma unroll
         for (int j = 0; j < NC * 3; ++j) k[j] = sc.sh[(int64_t)j * sc.n + g];
     } else {
 #pragma unroll
         for (int j = 0; j < NC * 3; ++j) k[j] = 0.0f;
     }
+    __syncthreads();
     for (int ci = 0; ci < it.ncam; ++ci) {
-        const int cl = it.cam0 + ci;
-        const CamParams cam = cams[cl];
+        const CamParams &cam = s_cam[ci];
         Projected P;
-        bool visible = in_range && project_gaussian(cam, po, a, b, m8, near, W, H, P);
-        const uint64_t slot = (uint64_t)cam_slot[cl] + (uint32_t)g;
+        bool visible = in_range && project_gaussian(cam, po, a, b, m8r, near, W, H, P);
+        const uint32_t slot = s_slot[ci] + (uint32_t)g;
         if (visible) {
             float dx = po.x - cam.C[0], dy = po.y - cam.C[1], dz = po.z - cam.C[2];
             const float inv = rsqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
@@ -129,49 +145,18 @@ __global__ __launch_bounds__(256) void k_project(
             recC[slot] = P.C;
             rect[slot] = make_uint2((uint32_t)P.x0 | ((uint32_t)P.x1 << 16),
                                     (uint32_t)P.y0 | ((uint32_t)P.y1 << 16));
+            zbits[slot] = __float_as_uint(P.C.y);
         }
         const uint64_t word = __ballot(visible);
         if (wave_live && __lane_id() == 0) vis[slot >> 6] = word;
     }
 }
 
-// ------------------------------------------------------------- compaction --
-// One wave per visibility word: the set bit of lane l goes to position
-// word_off[w] + popcount(word & lanes below l), so the output keeps the slot
-// order (camera-major, then Gaussian index) without atomics. Key =
-// (chunk-local camera << 31) | float bits of z (z > 0: the sign bit is clear
-// and the bits order as the values), value = slot.
-__global__ __launch_bounds__(256) void k_compact(const uint64_t *__restrict__ vis,
-                                                 const uint32_t *__restrict__ word_off,
-                                                 uint32_t n_words, const uint32_t *__restrict__ cam_slot,
-                                                 int n_cams, const float4 *__restrict__ recC,
-                                                 uint64_t *__restrict__ keys,
-                                                 uint32_t *__restrict__ vals)
-{
-    const uint32_t w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (w >= n_words) return;
-    const uint64_t word = vis[w];
-    if (word == 0) return;
-    const uint32_t lane = __lane_id();
-    if (!((word >> lane) & 1ull)) return;
-    const uint32_t slot = (w << 6) | lane;
-    // chunk-local camera owning the slot: last cam with cam_slot[cam] <= slot
-    int lo = 0, hi = n_cams - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (cam_slot[mid] <= slot) lo = mid; else hi = mid - 1;
-    }
-    const uint64_t below = lane == 0 ? 0ull : (word & (~0ull >> (64 - lane)));
-    const uint32_t pos = word_off[w] + (uint32_t)__popcll(below);
-    const float z = recC[slot].y;
-    keys[pos] = ((uint64_t)lo << 31) | (uint64_t)__float_as_uint(z);
-    vals[pos] = slot;
-}
-
 // ------------------------------------------------------ debug projection --
 template <int DEG>
-__global__ void k_debug_project(SceneDev sc, const CamParams *__restrict__ cam_p, float near,
-                                int W, int H, float *__restrict__ out)
+__global__ void k_debug_project(SceneDev sc, const int32_t *__restrict__ perm,
+                                const CamParams *__restrict__ cam_p, float near, int W, int H,
+                                float *__restrict__ out)
 {
     constexpr int NC = (DEG + 1) * (DEG + 1);
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -182,8 +167,8 @@ __global__ void k_debug_project(SceneDev sc, const CamParams *__restrict__ cam_p
     for (int j = 0; j < NC * 3; ++j) k[j] = sc.sh[(int64_t)j * sc.n + g];
     const float4 po = sc.pos_op[g];
     Projected P;
-    const bool visible = project_gaussian(cam, po, sc.m01[g], sc.m23[g], sc.m8[g], near, W, H, P);
-    float *o = out + g * 16;
+    const bool visible = project_gaussian(cam, po, sc.m01[g], sc.m23[g], sc.m8r[g], near, W, H, P);
+    float *o = out + (int64_t)perm[g] * 16;  // in the caller's index order
     for (int j = 0; j < 16; ++j) o[j] = 0.0f;
     if (!visible) {
         o[11] = 1.0f;  // x0 > x1 marks "not visible"
@@ -206,13 +191,13 @@ __global__ void k_debug_project(SceneDev sc, const CamParams *__restrict__ cam_p
 // ---------------------------------------------------------------- launch --
 void launch_scene_prep(const float *means, const float *scales, const float *quats,
                        const float *opacity, const float *sh, int64_t n, int ncoef, float4 *pos_op,
-                       float4 *m01, float4 *m23, float *m8, float *sh_planar, int *bad,
+                       float4 *m01, float4 *m23, float2 *m8r, float *sh_planar, int *bad,
                        hipStream_t st)
 {
     const int bs = 256;
     const int64_t grid = (n + bs - 1) / bs;
     hipLaunchKernelGGL(k_scene_prep, dim3((unsigned)grid), dim3(bs), 0, st, means, scales, quats,
-                       opacity, sh, n, ncoef, pos_op, m01, m23, m8, sh_planar, bad);
+                       opacity, sh, n, ncoef, pos_op, m01, m23, m8r, sh_planar, bad);
 }
 
 void launch_camera_setup(const float *poses, const float *intr, const int32_t *cam_global,
@@ -225,39 +210,29 @@ void launch_camera_setup(const float *poses, const float *intr, const int32_t *c
 
 void launch_project(int deg, const ProjItem *items, int n_items, const SceneDev *scenes,
                     const CamParams *cams, const uint32_t *cam_slot, float near, int W, int H,
-                    float4 *recA, float4 *recB, float4 *recC, uint2 *rect, uint64_t *vis,
-                    hipStream_t st)
+                    float4 *recA, float4 *recB, float4 *recC, uint2 *rect, uint32_t *zbits,
+                    uint64_t *vis, hipStream_t st)
 {
     if (n_items <= 0) return;
     dim3 grid(n_items), block(256);
     switch (deg) {
-    case 0: hipLaunchKernelGGL(k_project<0>, grid, block, 0, st, items, scenes, cams, cam_slot, near, W, H, recA, recB, recC, rect, vis); break;
-    case 1: hipLaunchKernelGGL(k_project<1>, grid, block, 0, st, items, scenes, cams, cam_slot, near, W, H, recA, recB, recC, rect, vis); break;
-    case 2: hipLaunchKernelGGL(k_project<2>, grid, block, 0, st, items, scenes, cams, cam_slot, near, W, H, recA, recB, recC, rect, vis); break;
-    default: hipLaunchKernelGGL(k_project<3>, grid, block, 0, st, items, scenes, cams, cam_slot, near, W, H, recA, recB, recC, rect, vis); break;
+    case 0: hipLaunchKernelGGL(k_project<0>, grid, block, 0, st, items, scenes, cams, cam_slot, near, W, H, recA, recB, recC, rect, zbits, vis); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, grid, block, 0, st, items, scenes, cams, cam_slot, near, W, H, recA, recB, recC, rect, zbits, vis); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, grid, block, 0, st, items, scenes, cams, cam_slot, near, W, H, recA, recB, recC, rect, zbits, vis); break;
+    default: hipLaunchKernelGGL(k_project<3>, grid, block, 0, st, items, scenes, cams, cam_slot, near, W, H, recA, recB, recC, rect, zbits, vis); break;
     }
 }
 
-void launch_compact(const uint64_t *vis, const uint32_t *word_off, uint32_t n_words,
-                    const uint32_t *cam_slot, int n_cams, const float4 *recC, uint64_t *keys,
-                    uint32_t *vals, hipStream_t st)
-{
-    if (n_words == 0) return;
-    const uint64_t threads = (uint64_t)n_words * 64;
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, vis,
-                       word_off, n_words, cam_slot, n_cams, recC, keys, vals);
-}
-
-void launch_debug_project(const SceneDev &sc, const CamParams *cam, float near, int W, int H,
-                          float *out, hipStream_t st)
+void launch_debug_project(const SceneDev &sc, const int32_t *perm, const CamParams *cam,
+                          float near, int W, int H, float *out, hipStream_t st)
 {
     const int bs = 256;
     dim3 grid((unsigned)((sc.n + bs - 1) / bs));
     switch (sc.deg) {
-    case 0: hipLaunchKernelGGL(k_debug_project<0>, grid, dim3(bs), 0, st, sc, cam, near, W, H, out); break;
-    case 1: hipLaunchKernelGGL(k_debug_project<1>, grid, dim3(bs), 0, st, sc, cam, near, W, H, out); break;
-    case 2: hipLaunchKernelGGL(k_debug_project<2>, grid, dim3(bs), 0, st, sc, cam, near, W, H, out); break;
-    default: hipLaunchKernelGGL(k_debug_project<3>, grid, dim3(bs), 0, st, sc, cam, near, W, H, out); break;
+    case 0: hipLaunchKernelGGL(k_debug_project<0>, grid, dim3(bs), 0, st, sc, perm, cam, near, W, H, out); break;
+    case 1: hipLaunchKernelGGL(k_debug_project<1>, grid, dim3(bs), 0, st, sc, perm, cam, near, W, H, out); break;
+    case 2: hipLaunchKernelGGL(k_debug_project<2>, grid, dim3(bs), 0, st, sc, perm, cam, near, W, H, out); break;
+    default: hipLaunchKernelGGL(k_debug_project<3>, grid, dim3(bs), 0, st, sc, perm, cam, near, W, H, out); break;
     }
 }
 

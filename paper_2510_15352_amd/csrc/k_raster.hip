@@ -6,38 +6,6 @@
 
 namespace gs {
 
-// ------------------------------------------------------------------ emit --
-// For the i-th record in (camera, depth, index) order write one instance per
-// overlapped tile: key = camera * tiles_per_cam + tile, value = slot.
-// Positions beyond the capacity are dropped (the overflow flag is raised by
-// k_finalize_counts and the host renders again with larger buffers).
-__global__ __launch_bounds__(256) void k_emit(const uint64_t *__restrict__ dkeys,
-                                              const uint32_t *__restrict__ dvals,
-                                              const uint32_t *__restrict__ n_vis,
-                                              const uint32_t *__restrict__ ioff,
-                                              const uint2 *__restrict__ rect, int tw, int th,
-                                              int tiles_x, int tiles_per_cam, uint32_t cap,
-                                              uint32_t *__restrict__ ikeys,
-                                              uint32_t *__restrict__ ivals)
-{
-    const uint32_t n = *n_vis;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t slot = dvals[i];
-        const uint32_t cl = (uint32_t)(dkeys[i] >> 31);
-        const uint2 r = rect[slot];
-        const int tx0 = (int)(r.x & 0xffffu) / tw, tx1 = (int)(r.x >> 16) / tw;
-        const int ty0 = (int)(r.y & 0xffffu) / th, ty1 = (int)(r.y >> 16) / th;
-        uint32_t o = ioff[i];
-        const uint32_t kbase = cl * (uint32_t)tiles_per_cam;
-        for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx, ++o)
-                if (o < cap) {
-                    ikeys[o] = kbase + (uint32_t)(ty * tiles_x + tx);
-                    ivals[o] = slot;
-                }
-    }
-}
-
 // counts[0] = visible pairs, counts[1] = instances, counts[2] = instances
 // kept (min(instances, cap)); flags accumulate over the chunks of a render.
 __global__ void k_finalize_counts(uint32_t *counts, uint32_t cap, RenderFlags *flags)
@@ -71,34 +39,65 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ ike
 }
 
 // -------------------------------------------------------------- raster --
+// One block per (camera, tile); each wave owns an 8x8 pixel sub-tile, one
+// pixel per lane. Per LDS batch of B records, every wave first keeps only
+// the records that can reach its 8x8 rectangle (may_touch, 64 records per
+// ballot, compacted with mbcnt into a per-wave index list), then walks that
+// list front to back. A skipped record has alpha < 1/255 at every pixel of
+// the wave, so the per-pixel result is the same as walking the full tile
+// list. The block stops when a barrier count says every pixel is done.
 template <int TW, int TH, int B, bool COUNT = false>
 __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &a, float4 *sA,
-                                            float4 *sB, float2 *sC, RenderFlags *cnt = nullptr)
+                                            float4 *sB, float4 *sC, uint16_t *sL,
+                                            RenderFlags *cnt = nullptr)
 {
+    static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are made of 8x8 wave sub-tiles");
     constexpr int NT = TW * TH;
+    constexpr int SX = TW / 8;
+    const int wave = (int)threadIdx.x >> 6;
+    const uint32_t lane = __lane_id();
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    const int lx = (int)threadIdx.x % TW, ly = (int)threadIdx.x / TW;
-    const int pxi = tx * TW + lx, pyi = ty * TH + ly;
+    const int wx0 = tx * TW + (wave % SX) * 8, wy0 = ty * TH + (wave / SX) * 8;
+    const int pxi = wx0 + (int)(lane & 7u), pyi = wy0 + (int)(lane >> 3);
     const bool inside = pxi < a.W && pyi < a.H;
     const float px = (float)pxi + 0.5f, py = (float)pyi + 0.5f;
+    // the wave's pixel rectangle, clipped to the image
+    const int wx1 = min(wx0 + 7, a.W - 1), wy1 = min(wy0 + 7, a.H - 1);
     const uint2 rg = a.ranges[(uint32_t)cl * (uint32_t)a.tiles_per_cam + (uint32_t)tile];
+    uint16_t *list = sL + wave * B;
+    const uint64_t lt = lanemask_lt();
     Pixel s;
     s.T = 1.0f; s.r = 0.0f; s.g = 0.0f; s.b = 0.0f; s.zw = 0.0f;
     s.done = !inside;
     uint32_t n_eval = 0, n_contrib = 0;
     for (uint32_t base = rg.x; base < rg.y; base += B) {
-        const int cnt = (int)min((uint32_t)B, rg.y - base);
+        const int cnt_b = (int)min((uint32_t)B, rg.y - base);
         __syncthreads();
-        for (int j = (int)threadIdx.x; j < cnt; j += NT) {
+        for (int j = (int)threadIdx.x; j < cnt_b; j += NT) {
             const uint32_t slot = a.ivals[base + j];
             sA[j] = a.recA[slot];
             sB[j] = a.recB[slot];
-            const float4 c = a.recC[slot];
-            sC[j] = make_float2(c.x, c.y);
+            sC[j] = a.recC[slot];
         }
         __syncthreads();
+        int n = 0;
+        if (__ballot(!s.done) != 0ull) {
+            for (int c0 = 0; c0 < cnt_b; c0 += 64) {
+                const int j = c0 + (int)lane;
+                bool hit = false;
+                if (j < cnt_b) {
+                    const float4 A = sA[j];
+                    hit = may_touch(A, sB[j].x, sC[j].z, wx0, wx1, wy0, wy1);
+                }
+                const uint64_t m = __ballot(hit);
+                if (hit) list[n + __popcll(m & lt)] = (uint16_t)j;
+                n += __popcll(m);
+            }
+        }
+        __syncthreads();  // per-wave lists written before they are read
         if (!s.done) {
-            for (int j = 0; j < cnt; ++j) {
+            for (int k = 0; k < n; ++k) {
+                const int j = list[k];
                 if (COUNT) {
                     const float Tb = s.T;
                     composite(s, px, py, sA[j], sB[j], sC[j]);
@@ -119,7 +118,7 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
             e += __shfl_down(e, d, 64);
             c += __shfl_down(c, d, 64);
         }
-        if (__lane_id() == 0) {
+        if (lane == 0) {
             atomicAdd(&cnt->pairs_eval, (unsigned long long)e);
             atomicAdd(&cnt->pairs_contrib, (unsigned long long)c);
         }
@@ -136,12 +135,15 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
     }
 }
 
+#define GS_RASTER_SHARED                      \
+    __shared__ float4 sA[B], sB[B], sC[B];    \
+    __shared__ uint16_t sL[(TW * TH / 64) * B];
+
 template <int TW, int TH, int B>
 __global__ __launch_bounds__(TW *TH) void k_raster(RasterArgs a)
 {
-    __shared__ float4 sA[B], sB[B];
-    __shared__ float2 sC[B];
-    raster_tile<TW, TH, B>((int)blockIdx.y, (int)blockIdx.x, a, sA, sB, sC);
+    GS_RASTER_SHARED
+    raster_tile<TW, TH, B>((int)blockIdx.y, (int)blockIdx.x, a, sA, sB, sC, sL);
 }
 
 // Instrumented grid form: same per-pixel arithmetic, plus counts of
@@ -149,9 +151,8 @@ __global__ __launch_bounds__(TW *TH) void k_raster(RasterArgs a)
 template <int TW, int TH, int B>
 __global__ __launch_bounds__(TW *TH) void k_raster_count(RasterArgs a, RenderFlags *cnt)
 {
-    __shared__ float4 sA[B], sB[B];
-    __shared__ float2 sC[B];
-    raster_tile<TW, TH, B, true>((int)blockIdx.y, (int)blockIdx.x, a, sA, sB, sC, cnt);
+    GS_RASTER_SHARED
+    raster_tile<TW, TH, B, true>((int)blockIdx.y, (int)blockIdx.x, a, sA, sB, sC, sL, cnt);
 }
 
 // Persistent form: a grid sized to the resident capacity pulls
@@ -160,8 +161,7 @@ template <int TW, int TH, int B>
 __global__ __launch_bounds__(TW *TH) void k_raster_persistent(RasterArgs a, uint32_t *queue,
                                                               uint32_t n_items)
 {
-    __shared__ float4 sA[B], sB[B];
-    __shared__ float2 sC[B];
+    GS_RASTER_SHARED
     __shared__ uint32_t s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(queue, 1u);
@@ -170,22 +170,11 @@ __global__ __launch_bounds__(TW *TH) void k_raster_persistent(RasterArgs a, uint
         __syncthreads();
         if (item >= n_items) break;
         raster_tile<TW, TH, B>((int)(item / (uint32_t)a.tiles_per_cam),
-                               (int)(item % (uint32_t)a.tiles_per_cam), a, sA, sB, sC);
+                               (int)(item % (uint32_t)a.tiles_per_cam), a, sA, sB, sC, sL);
     }
 }
 
 // --------------------------------------------------------------- launch --
-void launch_emit(const uint64_t *dkeys, const uint32_t *dvals, const uint32_t *n_vis,
-                 const uint32_t *ioff, const uint2 *rect, int tw, int th, int tiles_x,
-                 int tiles_per_cam, uint32_t cap, uint32_t *ikeys, uint32_t *ivals,
-                 uint32_t n_max, hipStream_t st)
-{
-    uint32_t blocks = (n_max + 255) / 256;
-    blocks = blocks < 1 ? 1 : (blocks > 16384 ? 16384 : blocks);
-    hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(256), 0, st, dkeys, dvals, n_vis, ioff, rect, tw,
-                       th, tiles_x, tiles_per_cam, cap, ikeys, ivals);
-}
-
 void launch_finalize_counts(uint32_t *counts, uint32_t cap, RenderFlags *flags, hipStream_t st)
 {
     hipLaunchKernelGGL(k_finalize_counts, dim3(1), dim3(1), 0, st, counts, cap, flags);

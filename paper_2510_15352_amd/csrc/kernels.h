@@ -22,11 +22,11 @@ struct RenderFlags {
 };
 
 struct ScanTemp {
-    uint32_t *partial;  // >= 1024 entries
+    uint32_t *partial;  // >= 4096 entries
 };
 
 struct SortTemp {
-    uint32_t *hist;  // >= 256 * 1024 entries
+    uint32_t *hist;  // >= 1024 * 4096 entries (digits x blocks)
     ScanTemp scan;
 };
 
@@ -42,37 +42,36 @@ struct RasterArgs {
 
 void launch_scene_prep(const float *means, const float *scales, const float *quats,
                        const float *opacity, const float *sh, int64_t n, int ncoef, float4 *pos_op,
-                       float4 *m01, float4 *m23, float *m8, float *sh_planar, int *bad,
+                       float4 *m01, float4 *m23, float2 *m8r, float *sh_planar, int *bad,
                        hipStream_t st);
 void launch_camera_setup(const float *poses, const float *intr, const int32_t *cam_global,
                          int n_cams, int W, int H, CamParams *out, hipStream_t st);
 void launch_project(int deg, const ProjItem *items, int n_items, const SceneDev *scenes,
                     const CamParams *cams, const uint32_t *cam_slot, float near, int W, int H,
-                    float4 *recA, float4 *recB, float4 *recC, uint2 *rect, uint64_t *vis,
-                    hipStream_t st);
-void launch_compact(const uint64_t *vis, const uint32_t *word_off, uint32_t n_words,
-                    const uint32_t *cam_slot, int n_cams, const float4 *recC, uint64_t *keys,
-                    uint32_t *vals, hipStream_t st);
-void launch_debug_project(const SceneDev &sc, const CamParams *cam, float near, int W, int H,
-                          float *out, hipStream_t st);
+                    float4 *recA, float4 *recB, float4 *recC, uint2 *rect, uint32_t *zbits,
+                    uint64_t *vis, hipStream_t st);
+void launch_debug_project(const SceneDev &sc, const int32_t *perm, const CamParams *cam,
+                          float near, int W, int H, float *out, hipStream_t st);
 
 void scan_u32(const uint32_t *in, const uint32_t *n_dev, uint32_t n_max, uint32_t *out,
               uint32_t *total_out, const ScanTemp &tmp, hipStream_t st);
-void scan_popcount(const uint64_t *words, uint32_t n_words, uint32_t *out, uint32_t *total_out,
-                   const ScanTemp &tmp, hipStream_t st);
-void scan_tile_counts(const uint32_t *vals, const uint2 *rect, int tw, int th,
-                      const uint32_t *n_dev, uint32_t n_max, uint32_t *out, uint32_t *total_out,
-                      const ScanTemp &tmp, hipStream_t st);
+// Order-preserving compaction of the set bits of the visibility words into
+// (camera << 31 | z bits, slot) pairs; *n_vis_out receives their number.
+void compact_visible(const uint64_t *vis, uint32_t n_words, const uint32_t *cam_slot, int n_cams,
+                     const uint32_t *zbits, uint64_t *keys, uint32_t *vals, uint32_t *n_vis_out,
+                     const ScanTemp &tmp, hipStream_t st);
+// Tile instances of the depth-sorted records: counts[1] = instances,
+// counts[2] = min(instances, cap), flags updated; entries past cap dropped.
+void emit_instances(const uint64_t *dkeys, const uint32_t *dvals, const uint32_t *n_vis,
+                    uint32_t n_max, const uint2 *rect, int tw, int th, int tiles_x,
+                    int tiles_per_cam, uint32_t cap, uint32_t *ikeys, uint32_t *ivals,
+                    uint32_t *counts, RenderFlags *flags, const ScanTemp &tmp, hipStream_t st);
 // Return 0 if the sorted data ended in (k0, v0), 1 if in (k1, v1).
 int radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, const uint32_t *n_dev,
                    uint32_t n_max, int bits, const SortTemp &tmp, hipStream_t st);
 int radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *n_dev,
                    uint32_t n_max, int bits, const SortTemp &tmp, hipStream_t st);
 
-void launch_emit(const uint64_t *dkeys, const uint32_t *dvals, const uint32_t *n_vis,
-                 const uint32_t *ioff, const uint2 *rect, int tw, int th, int tiles_x,
-                 int tiles_per_cam, uint32_t cap, uint32_t *ikeys, uint32_t *ivals,
-                 uint32_t n_max, hipStream_t st);
 void launch_finalize_counts(uint32_t *counts, uint32_t cap, RenderFlags *flags, hipStream_t st);
 void launch_zero_u32(uint32_t *p, uint64_t n, hipStream_t st);
 void launch_ranges(const uint32_t *ikeys, const uint32_t *n_dev, uint2 *ranges, uint32_t n_max,

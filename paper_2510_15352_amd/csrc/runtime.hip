@@ -64,8 +64,10 @@ struct DevBuf {
 struct Scene {
     int64_t n = 0;
     int deg = 0;
+    DevBuf<int32_t> perm;  // caller's index of each stored Gaussian
     DevBuf<float4> pos_op, m01, m23;
-    DevBuf<float> m8, sh;
+    DevBuf<float2> m8r;
+    DevBuf<float> sh;
     int graph_refs = 0;
 };
 
@@ -117,11 +119,10 @@ struct gs_ctx {
     // workspace
     DevBuf<float4> recA, recB, recC;
     DevBuf<uint2> rect;
+    DevBuf<uint32_t> zbits;
     DevBuf<uint64_t> vis;
-    DevBuf<uint32_t> word_off;
     DevBuf<uint64_t> dkeys[2];
     DevBuf<uint32_t> dvals[2];
-    DevBuf<uint32_t> ioff;
     DevBuf<uint32_t> ikeys[2], ivals[2];
     DevBuf<uint2> ranges;
     DevBuf<CamParams> cams;
@@ -187,7 +188,7 @@ void sync_scene_table(gs_ctx *ctx)
             d.pos_op = s.pos_op.p;
             d.m01 = s.m01.p;
             d.m23 = s.m23.p;
-            d.m8 = s.m8.p;
+            d.m8r = s.m8r.p;
             d.sh = s.sh.p;
             d.n = s.n;
             d.deg = s.deg;
@@ -318,13 +319,12 @@ bool ensure_workspace(gs_ctx *ctx, const Plan &P)
     moved |= ctx->recB.reserve(slots);
     moved |= ctx->recC.reserve(slots);
     moved |= ctx->rect.reserve(slots);
+    moved |= ctx->zbits.reserve(slots);
     moved |= ctx->vis.reserve(slots / 64);
-    moved |= ctx->word_off.reserve(slots / 64);
     for (int i = 0; i < 2; ++i) {
         moved |= ctx->dkeys[i].reserve(slots);
         moved |= ctx->dvals[i].reserve(slots);
     }
-    moved |= ctx->ioff.reserve(slots);
     if (ctx->inst_cap == 0) ctx->inst_cap = std::max<uint64_t>(uint64_t(1) << 20, slots / 2);
     ctx->inst_cap = std::min<uint64_t>(ctx->inst_cap, uint64_t(0xFFFFFFF0u));
     for (int i = 0; i < 2; ++i) {
@@ -336,8 +336,8 @@ bool ensure_workspace(gs_ctx *ctx, const Plan &P)
     moved |= ctx->counts.reserve(4);
     moved |= ctx->flags.reserve(1);
     moved |= ctx->queue.reserve(1);
-    moved |= ctx->scan_partial.reserve(1024);
-    moved |= ctx->sort_hist.reserve(256 * 1024);
+    moved |= ctx->scan_partial.reserve(4096);
+    moved |= ctx->sort_hist.reserve(1024 * 4096);
     if (moved) ++ctx->generation;
     return moved;
 }
@@ -402,13 +402,12 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
             if (c.item_cnt[d])
                 launch_project(d, P.d_items.p + c.item_off[d], c.item_cnt[d], ctx->d_scenes.p, cams,
                                cam_slot, near, P.W, P.H, ctx->recA.p, ctx->recB.p, ctx->recC.p,
-                               ctx->rect.p, ctx->vis.p, st);
+                               ctx->rect.p, ctx->zbits.p, ctx->vis.p, st);
         T.end(GS_STAGE_PROJECT, t0);
         // visible count and order-preserving compaction
         t0 = T.begin();
-        scan_popcount(ctx->vis.p, n_words, ctx->word_off.p, ctx->counts.p + 0, scan, st);
-        launch_compact(ctx->vis.p, ctx->word_off.p, n_words, cam_slot, c.count, ctx->recC.p,
-                       ctx->dkeys[0].p, ctx->dvals[0].p, st);
+        compact_visible(ctx->vis.p, n_words, cam_slot, c.count, ctx->zbits.p, ctx->dkeys[0].p,
+                        ctx->dvals[0].p, ctx->counts.p + 0, scan, st);
         T.end(GS_STAGE_COMPACT, t0);
         // depth sort: key = (camera << 31) | z bits (z > 0, sign bit clear)
         const int dbits = 31 + bits_for((uint64_t)c.count);
@@ -417,14 +416,11 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
                                      ctx->dvals[1].p, ctx->counts.p + 0, (uint32_t)c.slots, dbits,
                                      sort, st);
         T.end(GS_STAGE_DEPTH_SORT, t0);
-        // tile counts in depth order -> instance offsets
+        // tile instances in (camera, depth, index) order
         t0 = T.begin();
-        scan_tile_counts(ctx->dvals[r].p, ctx->rect.p, ch.tw, ch.th, ctx->counts.p + 0,
-                         (uint32_t)c.slots, ctx->ioff.p, ctx->counts.p + 1, scan, st);
-        launch_finalize_counts(ctx->counts.p, cap, ctx->flags.p, st);
-        launch_emit(ctx->dkeys[r].p, ctx->dvals[r].p, ctx->counts.p + 0, ctx->ioff.p, ctx->rect.p,
-                    ch.tw, ch.th, P.tiles_x, P.tiles_per_cam, cap, ctx->ikeys[0].p,
-                    ctx->ivals[0].p, (uint32_t)c.slots, st);
+        emit_instances(ctx->dkeys[r].p, ctx->dvals[r].p, ctx->counts.p + 0, (uint32_t)c.slots,
+                       ctx->rect.p, ch.tw, ch.th, P.tiles_x, P.tiles_per_cam, cap, ctx->ikeys[0].p,
+                       ctx->ivals[0].p, ctx->counts.p, ctx->flags.p, scan, st);
         T.end(GS_STAGE_EMIT, t0);
         // stable tile sort keeps the depth order inside each tile
         const uint64_t n_tiles = (uint64_t)c.count * P.tiles_per_cam;
@@ -704,30 +700,78 @@ int gs_upload_scene(gs_ctx *ctx, const gs_scene_desc *d, int32_t *scene_id_out)
         s->pos_op.reserve(n);
         s->m01.reserve(n);
         s->m23.reserve(n);
-        s->m8.reserve(n);
+        s->m8r.reserve(n);
         s->sh.reserve((size_t)n * nc * 3);
         DevBuf<float> tmp;
         DevBuf<int> bad;
         bad.reserve(1);
         HIP_CHECK(hipMemset(bad.p, 0, sizeof(int)));
-        const float *m = d->means, *sc = d->scales, *q = d->quats, *op = d->opacity, *sh = d->sh;
-        if (d->mem_kind == GS_MEM_HOST) {
-            const size_t counts[5] = {(size_t)n * 3, (size_t)n * 3, (size_t)n * 4, (size_t)n,
-                                      (size_t)n * nc * 3};
-            size_t total = 0;
-            for (size_t c : counts) total += c;
-            tmp.reserve(total);
-            const float *src[5] = {d->means, d->scales, d->quats, d->opacity, d->sh};
-            const float **dst[5] = {&m, &sc, &q, &op, &sh};
-            size_t off = 0;
+        // Host copies of the arrays, stored in Morton order of the means so that
+        // the Gaussians of one wave are spatial neighbours (coherent culling).
+        const size_t counts[5] = {(size_t)n * 3, (size_t)n * 3, (size_t)n * 4, (size_t)n,
+                                  (size_t)n * nc * 3};
+        const size_t widths[5] = {3, 3, 4, 1, (size_t)nc * 3};
+        const float *src[5] = {d->means, d->scales, d->quats, d->opacity, d->sh};
+        std::vector<std::vector<float>> host(5);
+        for (int i = 0; i < 5; ++i) {
+            host[i].resize(counts[i]);
+            if (d->mem_kind == GS_MEM_HOST)
+                std::memcpy(host[i].data(), src[i], counts[i] * sizeof(float));
+            else
+                HIP_CHECK(hipMemcpy(host[i].data(), src[i], counts[i] * sizeof(float),
+                                    hipMemcpyDeviceToHost));
+        }
+        const float *hm = host[0].data();
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int64_t g = 0; g < n; ++g)
+            for (int a = 0; a < 3; ++a) {
+                const float v = hm[g * 3 + a];
+                if (!std::isfinite(v))
+                    return fail(ctx, GS_ERR_BAD_SCENE, "scene has non-finite means");
+                lo[a] = std::min(lo[a], v);
+                hi[a] = std::max(hi[a], v);
+            }
+        std::vector<std::pair<uint64_t, int32_t>> code(n);
+        for (int64_t g = 0; g < n; ++g) {
+            uint64_t c = 0;
+            uint32_t qv[3];
+            for (int a = 0; a < 3; ++a) {
+                const float span = hi[a] - lo[a];
+                const float t = span > 0 ? (hm[g * 3 + a] - lo[a]) / span : 0.0f;
+                qv[a] = (uint32_t)std::min(2097151.0f, std::max(0.0f, t * 2097151.0f));
+            }
+            for (int bit = 20; bit >= 0; --bit)
+                for (int a = 0; a < 3; ++a) c = (c << 1) | ((qv[a] >> bit) & 1u);
+            code[g] = {c, (int32_t)g};
+        }
+        std::sort(code.begin(), code.end());
+        std::vector<float> packed;
+        size_t total = 0;
+        for (size_t c : counts) total += c;
+        packed.resize(total);
+        size_t off[5];
+        {
+            size_t o = 0;
             for (int i = 0; i < 5; ++i) {
-                HIP_CHECK(hipMemcpy(tmp.p + off, src[i], counts[i] * sizeof(float),
-                                    hipMemcpyHostToDevice));
-                *dst[i] = tmp.p + off;
-                off += counts[i];
+                off[i] = o;
+                o += counts[i];
             }
         }
-        launch_scene_prep(m, sc, q, op, sh, n, nc, s->pos_op.p, s->m01.p, s->m23.p, s->m8.p,
+        std::vector<int32_t> perm(n);
+        for (int64_t g = 0; g < n; ++g) {
+            const int32_t from = code[g].second;
+            perm[g] = from;
+            for (int i = 0; i < 5; ++i)
+                std::memcpy(packed.data() + off[i] + (size_t)g * widths[i],
+                            host[i].data() + (size_t)from * widths[i], widths[i] * sizeof(float));
+        }
+        tmp.reserve(total);
+        HIP_CHECK(hipMemcpy(tmp.p, packed.data(), total * sizeof(float), hipMemcpyHostToDevice));
+        s->perm.reserve(n);
+        HIP_CHECK(hipMemcpy(s->perm.p, perm.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
+        const float *m = tmp.p + off[0], *sc = tmp.p + off[1], *q = tmp.p + off[2],
+                    *op = tmp.p + off[3], *sh = tmp.p + off[4];
+        launch_scene_prep(m, sc, q, op, sh, n, nc, s->pos_op.p, s->m01.p, s->m23.p, s->m8r.p,
                           s->sh.p, bad.p, nullptr);
         HIP_CHECK(hipGetLastError());
         int hbad = 0;
@@ -858,11 +902,11 @@ int gs_debug_project(gs_ctx *ctx, int32_t scene_id, const float *pose, const flo
         sd.pos_op = s.pos_op.p;
         sd.m01 = s.m01.p;
         sd.m23 = s.m23.p;
-        sd.m8 = s.m8.p;
+        sd.m8r = s.m8r.p;
         sd.sh = s.sh.p;
         sd.n = s.n;
         sd.deg = s.deg;
-        launch_debug_project(sd, ctx->cams.p, near_plane, width, height, out, nullptr);
+        launch_debug_project(sd, s.perm.p, ctx->cams.p, near_plane, width, height, out, nullptr);
         HIP_CHECK(hipGetLastError());
         HIP_CHECK(hipDeviceSynchronize());
         return GS_OK;
