@@ -86,7 +86,10 @@ typedef struct {
     int32_t timing;    /* record HIP events around every stage (eager renders only) */
     int32_t count_pairs; /* also count contributing / evaluated (pixel, Gaussian) pairs
                             with an instrumented raster kernel (slower; for measurement) */
-    int32_t reserved[3];
+    int32_t streams;   /* BATCHED: 1 = one chunk pipeline; 0 or 2 = two pipelines on two
+                          streams, the raster of one chunk overlapping the next chunk's
+                          projection and sorts (timing renders always use one) */
+    int32_t reserved[2];
 } gs_render_opts;
 
 /* Stages timed when gs_render_opts.timing is set (indices of stage_ms). */

@@ -45,7 +45,7 @@ class RenderOpts(ctypes.Structure):
                 ("lds_batch", ctypes.c_int32), ("chunk_cams", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("count_pairs", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("streams", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 STAGES = ("setup", "project", "compact", "depth_sort", "emit", "tile_sort", "ranges", "raster")
 
@@ -175,7 +175,8 @@ class Renderer:
 
     # ------------------------------------------------------------ render --
     def opts(self, mode="batched", tile=None, lds_batch=0, chunk_cams=0, persistent=-1,
-             use_graph=False, near=0.2, bg=(0.0, 0.0, 0.0), timing=False, count_pairs=False):
+             use_graph=False, near=0.2, bg=(0.0, 0.0, 0.0), timing=False, count_pairs=False,
+             streams=0):
         o = RenderOpts()
         self.lib.gs_default_opts(ctypes.byref(o))
         o.mode = GS_MODE_PLAIN if mode == "plain" else GS_MODE_BATCHED
@@ -187,6 +188,7 @@ class Renderer:
         o.use_graph = int(bool(use_graph))
         o.timing = int(bool(timing))
         o.count_pairs = int(bool(count_pairs))
+        o.streams = int(streams)
         o.near_plane = float(near)
         for i in range(3):
             o.bg[i] = float(bg[i])

@@ -99,6 +99,24 @@ struct Plan {
     DevBuf<ProjItem> d_items;
 };
 
+// Buffers of one chunk pipeline.
+struct Lane {
+    DevBuf<float4> recA, recB, recC;
+    DevBuf<uint2> rect;
+    DevBuf<uint32_t> zbits;
+    DevBuf<uint64_t> vis;
+    DevBuf<uint64_t> dkeys[2];
+    DevBuf<uint32_t> dvals[2];
+    DevBuf<uint32_t> ikeys[2], ivals[2];
+    DevBuf<uint2> ranges;
+    DevBuf<uint32_t> counts;  // [0] visible, [1] instances, [2] kept
+    DevBuf<RenderFlags> flags;
+    DevBuf<uint32_t> queue;
+    DevBuf<uint32_t> scan_partial, sort_hist;
+};
+
+constexpr int kLanes = 2;
+
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -116,26 +134,19 @@ struct gs_ctx {
     DevBuf<SceneDev> d_scenes;
     bool scenes_dirty = true;
 
-    // workspace
-    DevBuf<float4> recA, recB, recC;
-    DevBuf<uint2> rect;
-    DevBuf<uint32_t> zbits;
-    DevBuf<uint64_t> vis;
-    DevBuf<uint64_t> dkeys[2];
-    DevBuf<uint32_t> dvals[2];
-    DevBuf<uint32_t> ikeys[2], ivals[2];
-    DevBuf<uint2> ranges;
+    // workspace: two lanes, so that one chunk's raster can overlap the next
+    // chunk's projection and sorts on a second stream
+    Lane lanes[kLanes];
     DevBuf<CamParams> cams;
-    DevBuf<uint32_t> counts;  // [0] visible, [1] instances, [2] kept
-    DevBuf<DevFlags> flags;
-    DevBuf<uint32_t> queue;
-    DevBuf<uint32_t> scan_partial, sort_hist;
     DevBuf<float> dbg_pose;
     uint64_t inst_cap = 0;
     int generation = 0;  // bumps whenever a workspace buffer moves
 
-    DevFlags *host_flags = nullptr;  // pinned
+    DevFlags *host_flags = nullptr;  // pinned, one per lane
     hipStream_t capture_stream = nullptr;
+    hipStream_t capture_aux = nullptr;  // second stream of a captured render
+    hipStream_t aux_stream = nullptr;   // second stream of an eager render
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
     std::vector<hipEvent_t> events;  // pool for stage timing
     std::map<std::string, std::unique_ptr<GraphEntry>> graphs;
@@ -310,34 +321,36 @@ std::unique_ptr<Plan> make_plan(gs_ctx *ctx, int n_cams, const int32_t *scene_id
     return P;
 }
 
-// Grow the workspace for a plan; returns true if any buffer moved.
-bool ensure_workspace(gs_ctx *ctx, const Plan &P)
+// Grow the workspace of `n_lanes` lanes for a plan; returns true if any
+// buffer moved.
+bool ensure_workspace(gs_ctx *ctx, const Plan &P, int n_lanes)
 {
     bool moved = false;
     const uint64_t slots = std::max<uint64_t>(P.max_slots, 64);
-    moved |= ctx->recA.reserve(slots);
-    moved |= ctx->recB.reserve(slots);
-    moved |= ctx->recC.reserve(slots);
-    moved |= ctx->rect.reserve(slots);
-    moved |= ctx->zbits.reserve(slots);
-    moved |= ctx->vis.reserve(slots / 64);
-    for (int i = 0; i < 2; ++i) {
-        moved |= ctx->dkeys[i].reserve(slots);
-        moved |= ctx->dvals[i].reserve(slots);
-    }
     if (ctx->inst_cap == 0) ctx->inst_cap = std::max<uint64_t>(uint64_t(1) << 20, slots / 2);
     ctx->inst_cap = std::min<uint64_t>(ctx->inst_cap, uint64_t(0xFFFFFFF0u));
-    for (int i = 0; i < 2; ++i) {
-        moved |= ctx->ikeys[i].reserve(ctx->inst_cap);
-        moved |= ctx->ivals[i].reserve(ctx->inst_cap);
+    for (int l = 0; l < n_lanes; ++l) {
+        Lane &L = ctx->lanes[l];
+        moved |= L.recA.reserve(slots);
+        moved |= L.recB.reserve(slots);
+        moved |= L.recC.reserve(slots);
+        moved |= L.rect.reserve(slots);
+        moved |= L.zbits.reserve(slots);
+        moved |= L.vis.reserve(slots / 64);
+        for (int i = 0; i < 2; ++i) {
+            moved |= L.dkeys[i].reserve(slots);
+            moved |= L.dvals[i].reserve(slots);
+            moved |= L.ikeys[i].reserve(ctx->inst_cap);
+            moved |= L.ivals[i].reserve(ctx->inst_cap);
+        }
+        moved |= L.ranges.reserve((uint64_t)P.max_chunk_cams * P.tiles_per_cam);
+        moved |= L.counts.reserve(4);
+        moved |= L.flags.reserve(1);
+        moved |= L.queue.reserve(1);
+        moved |= L.scan_partial.reserve(4096);
+        moved |= L.sort_hist.reserve(1024 * 4096);
     }
-    moved |= ctx->ranges.reserve((uint64_t)P.max_chunk_cams * P.tiles_per_cam);
     moved |= ctx->cams.reserve(std::max(P.n_cams, 1));
-    moved |= ctx->counts.reserve(4);
-    moved |= ctx->flags.reserve(1);
-    moved |= ctx->queue.reserve(1);
-    moved |= ctx->scan_partial.reserve(4096);
-    moved |= ctx->sort_hist.reserve(1024 * 4096);
     if (moved) ++ctx->generation;
     return moved;
 }
@@ -376,24 +389,37 @@ struct StageTimer {
 };
 
 // Enqueue the whole render of a plan on `st` (also used under capture).
+// With two lanes, odd chunks run on `aux`, forked from `st` after the camera
+// setup and joined back at the end; each lane's chunks are serial on its
+// stream, so a lane's buffers are reused only after its previous raster.
 void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float *intr, float near,
                     const float bg[3], float *rgb, float *depth, float *alpha, hipStream_t st,
-                    StageTimer *tm = nullptr, bool count_pairs = false)
+                    hipStream_t aux, int n_lanes, StageTimer *tm = nullptr,
+                    bool count_pairs = false)
 {
     StageTimer off{ctx, st, false};
     StageTimer &T = tm ? *tm : off;
     const Choice &ch = P.ch;
-    ScanTemp scan{ctx->scan_partial.p};
-    SortTemp sort{ctx->sort_hist.p, scan};
     const uint32_t cap = (uint32_t)ctx->inst_cap;
     size_t t0 = T.begin();
-    launch_zero_u32((uint32_t *)ctx->flags.p, sizeof(DevFlags) / 4, st);
+    for (int l = 0; l < n_lanes; ++l)
+        launch_zero_u32((uint32_t *)ctx->lanes[l].flags.p, sizeof(DevFlags) / 4, st);
     launch_camera_setup(poses, intr, P.d_order.p, P.n_cams, P.W, P.H, ctx->cams.p, st);
     T.end(GS_STAGE_SETUP, t0);
+    if (n_lanes > 1) {
+        HIP_CHECK(hipEventRecord(ctx->ev_fork, st));
+        HIP_CHECK(hipStreamWaitEvent(aux, ctx->ev_fork, 0));
+    }
     int persistent_blocks = 0;
     if (ch.persistent)
         persistent_blocks = raster_occupancy(ch.tw, ch.th, ch.batch) * std::max(ctx->cu_count, 1);
-    for (const Chunk &c : P.chunks) {
+    for (size_t ci = 0; ci < P.chunks.size(); ++ci) {
+        const Chunk &c = P.chunks[ci];
+        Lane &L = ctx->lanes[ci % n_lanes];
+        const hipStream_t s = (ci % n_lanes) ? aux : st;
+        T.st = s;
+        ScanTemp scan{L.scan_partial.p};
+        SortTemp sort{L.sort_hist.p, scan};
         const CamParams *cams = ctx->cams.p + c.start;
         const uint32_t *cam_slot = P.d_cam_slot.p + c.start;
         const uint32_t n_words = (uint32_t)(c.slots / 64);
@@ -401,44 +427,43 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
         for (int d = 0; d < 4; ++d)
             if (c.item_cnt[d])
                 launch_project(d, P.d_items.p + c.item_off[d], c.item_cnt[d], ctx->d_scenes.p, cams,
-                               cam_slot, near, P.W, P.H, ctx->recA.p, ctx->recB.p, ctx->recC.p,
-                               ctx->rect.p, ctx->zbits.p, ctx->vis.p, st);
+                               cam_slot, near, P.W, P.H, L.recA.p, L.recB.p, L.recC.p, L.rect.p,
+                               L.zbits.p, L.vis.p, s);
         T.end(GS_STAGE_PROJECT, t0);
         // visible count and order-preserving compaction
         t0 = T.begin();
-        compact_visible(ctx->vis.p, n_words, cam_slot, c.count, ctx->zbits.p, ctx->dkeys[0].p,
-                        ctx->dvals[0].p, ctx->counts.p + 0, scan, st);
+        compact_visible(L.vis.p, n_words, cam_slot, c.count, L.zbits.p, L.dkeys[0].p,
+                        L.dvals[0].p, L.counts.p + 0, scan, s);
         T.end(GS_STAGE_COMPACT, t0);
         // depth sort: key = (camera << 31) | z bits (z > 0, sign bit clear)
         const int dbits = 31 + bits_for((uint64_t)c.count);
         t0 = T.begin();
-        const int r = radix_sort_u64(ctx->dkeys[0].p, ctx->dvals[0].p, ctx->dkeys[1].p,
-                                     ctx->dvals[1].p, ctx->counts.p + 0, (uint32_t)c.slots, dbits,
-                                     sort, st);
+        const int r = radix_sort_u64(L.dkeys[0].p, L.dvals[0].p, L.dkeys[1].p, L.dvals[1].p,
+                                     L.counts.p + 0, (uint32_t)c.slots, dbits, sort, s);
         T.end(GS_STAGE_DEPTH_SORT, t0);
         // tile instances in (camera, depth, index) order
         t0 = T.begin();
-        emit_instances(ctx->dkeys[r].p, ctx->dvals[r].p, ctx->counts.p + 0, (uint32_t)c.slots,
-                       ctx->rect.p, ch.tw, ch.th, P.tiles_x, P.tiles_per_cam, cap, ctx->ikeys[0].p,
-                       ctx->ivals[0].p, ctx->counts.p, ctx->flags.p, scan, st);
+        emit_instances(L.dkeys[r].p, L.dvals[r].p, L.counts.p + 0, (uint32_t)c.slots, L.rect.p,
+                       ch.tw, ch.th, P.tiles_x, P.tiles_per_cam, cap, L.ikeys[0].p, L.ivals[0].p,
+                       L.counts.p, L.flags.p, scan, s);
         T.end(GS_STAGE_EMIT, t0);
         // stable tile sort keeps the depth order inside each tile
         const uint64_t n_tiles = (uint64_t)c.count * P.tiles_per_cam;
         t0 = T.begin();
-        const int r2 = radix_sort_u32(ctx->ikeys[0].p, ctx->ivals[0].p, ctx->ikeys[1].p,
-                                      ctx->ivals[1].p, ctx->counts.p + 2, cap,
-                                      std::max(1, bits_for(n_tiles)), sort, st);
+        const int r2 = radix_sort_u32(L.ikeys[0].p, L.ivals[0].p, L.ikeys[1].p, L.ivals[1].p,
+                                      L.counts.p + 2, cap, std::max(1, bits_for(n_tiles)), sort,
+                                      s);
         T.end(GS_STAGE_TILE_SORT, t0);
         t0 = T.begin();
-        launch_zero_u32((uint32_t *)ctx->ranges.p, n_tiles * 2, st);
-        launch_ranges(ctx->ikeys[r2].p, ctx->counts.p + 2, ctx->ranges.p, cap, st);
+        launch_zero_u32((uint32_t *)L.ranges.p, n_tiles * 2, s);
+        launch_ranges(L.ikeys[r2].p, L.counts.p + 2, L.ranges.p, cap, s);
         T.end(GS_STAGE_RANGES, t0);
         RasterArgs a;
-        a.ranges = ctx->ranges.p;
-        a.ivals = ctx->ivals[r2].p;
-        a.recA = ctx->recA.p;
-        a.recB = ctx->recB.p;
-        a.recC = ctx->recC.p;
+        a.ranges = L.ranges.p;
+        a.ivals = L.ivals[r2].p;
+        a.recA = L.recA.p;
+        a.recB = L.recB.p;
+        a.recC = L.recC.p;
         a.cam_global = P.d_order.p + c.start;
         a.tiles_x = P.tiles_x;
         a.tiles_per_cam = P.tiles_per_cam;
@@ -451,11 +476,34 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
         a.depth = depth;
         a.alpha = alpha;
         t0 = T.begin();
-        launch_raster(ch.tw, ch.th, ch.batch, ch.persistent != 0, a, c.count, ctx->queue.p,
-                      persistent_blocks, count_pairs ? ctx->flags.p : nullptr, st);
+        launch_raster(ch.tw, ch.th, ch.batch, ch.persistent != 0, a, c.count, L.queue.p,
+                      persistent_blocks, count_pairs ? L.flags.p : nullptr, s);
         T.end(GS_STAGE_RASTER, t0);
     }
+    if (n_lanes > 1) {
+        HIP_CHECK(hipEventRecord(ctx->ev_join, aux));
+        HIP_CHECK(hipStreamWaitEvent(st, ctx->ev_join, 0));
+    }
     HIP_CHECK(hipGetLastError());
+}
+
+// Copy every lane's flags to the pinned host block on `st` (after the join).
+void read_flags(gs_ctx *ctx, int n_lanes, hipStream_t st, DevFlags &out)
+{
+    for (int l = 0; l < n_lanes; ++l)
+        HIP_CHECK(hipMemcpyAsync(ctx->host_flags + l, ctx->lanes[l].flags.p, sizeof(DevFlags),
+                                 hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    out = DevFlags{};
+    for (int l = 0; l < n_lanes; ++l) {
+        const DevFlags &f = ctx->host_flags[l];
+        out.overflow |= f.overflow;
+        out.max_inst = std::max(out.max_inst, f.max_inst);
+        out.visible += f.visible;
+        out.instances += f.instances;
+        out.pairs_contrib += f.pairs_contrib;
+        out.pairs_eval += f.pairs_eval;
+    }
 }
 
 void clear_graphs(gs_ctx *ctx)
@@ -518,37 +566,41 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
     if (ch.chunk < 1) return fail(ctx, GS_ERR_INVALID_ARG, "chunk_cams must be >= 1");
     const bool batched = o.mode != GS_MODE_PLAIN;
     const bool use_graph = batched && o.use_graph;
+    // two lanes (overlapped chunk pipelines) for batched renders, except when
+    // timing stages (their durations are measured one kernel at a time)
+    const int n_lanes = (batched && !o.timing && o.streams != 1) ? kLanes : 1;
     sync_scene_table(ctx);
     ctx->last = gs_stats{};
     int regrows = 0;
     for (int attempt = 0; attempt < 6; ++attempt) {
         StageTimer timer{ctx, st, o.timing != 0};
+        DevFlags f;
         if (!use_graph) {
             // eager: the plain form is the same kernel sequence with one camera per chunk
             std::unique_ptr<Plan> P = make_plan(ctx, n_cams, scene_ids, W, H, ch);
-            if (ensure_workspace(ctx, *P)) clear_graphs(ctx);
-            enqueue_render(ctx, *P, poses, intr, o.near_plane, o.bg, rgb, depth, alpha, st, &timer,
-                           o.count_pairs != 0);
-            HIP_CHECK(hipMemcpyAsync(ctx->host_flags, ctx->flags.p, sizeof(DevFlags),
-                                     hipMemcpyDeviceToHost, st));
-            HIP_CHECK(hipStreamSynchronize(st));
+            if (ensure_workspace(ctx, *P, n_lanes)) clear_graphs(ctx);
+            enqueue_render(ctx, *P, poses, intr, o.near_plane, o.bg, rgb, depth, alpha, st,
+                           ctx->aux_stream, n_lanes, &timer, o.count_pairs != 0);
+            read_flags(ctx, n_lanes, st, f);
         } else {
             std::string key = graph_key(n_cams, scene_ids, W, H, ch, o.near_plane, o.bg, poses,
-                                        intr, rgb, depth, alpha, ctx->generation, ctx->inst_cap);
+                                        intr, rgb, depth, alpha, ctx->generation, ctx->inst_cap) +
+                              "|l" + std::to_string(n_lanes);
             auto it = ctx->graphs.find(key);
             if (it == ctx->graphs.end()) {
                 auto g = std::make_unique<GraphEntry>();
                 g->plan = make_plan(ctx, n_cams, scene_ids, W, H, ch);
-                if (ensure_workspace(ctx, *g->plan)) {
+                if (ensure_workspace(ctx, *g->plan, n_lanes)) {
                     clear_graphs(ctx);
                     key = graph_key(n_cams, scene_ids, W, H, ch, o.near_plane, o.bg, poses, intr,
-                                    rgb, depth, alpha, ctx->generation, ctx->inst_cap);
+                                    rgb, depth, alpha, ctx->generation, ctx->inst_cap) +
+                          "|l" + std::to_string(n_lanes);
                 }
                 HIP_CHECK(hipStreamBeginCapture(ctx->capture_stream,
                                                 hipStreamCaptureModeThreadLocal));
                 try {
                     enqueue_render(ctx, *g->plan, poses, intr, o.near_plane, o.bg, rgb, depth,
-                                   alpha, ctx->capture_stream);
+                                   alpha, ctx->capture_stream, ctx->capture_aux, n_lanes);
                 } catch (...) {
                     hipGraph_t junk = nullptr;
                     (void)hipStreamEndCapture(ctx->capture_stream, &junk);
@@ -563,11 +615,8 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
                 it = ctx->graphs.emplace(key, std::move(g)).first;
             }
             HIP_CHECK(hipGraphLaunch(it->second->exec, st));
-            HIP_CHECK(hipMemcpyAsync(ctx->host_flags, ctx->flags.p, sizeof(DevFlags),
-                                     hipMemcpyDeviceToHost, st));
-            HIP_CHECK(hipStreamSynchronize(st));
+            read_flags(ctx, n_lanes, st, f);
         }
-        const DevFlags f = *ctx->host_flags;
         ctx->last = gs_stats{};
         ctx->last.visible = (int64_t)f.visible;
         ctx->last.instances = (int64_t)f.instances;
@@ -647,8 +696,13 @@ int gs_create(int hip_device, gs_ctx **out)
         hipDeviceProp_t prop;
         HIP_CHECK(hipGetDeviceProperties(&prop, hip_device));
         ctx->cu_count = prop.multiProcessorCount;
-        HIP_CHECK(hipHostMalloc((void **)&ctx->host_flags, sizeof(DevFlags), hipHostMallocDefault));
+        HIP_CHECK(hipHostMalloc((void **)&ctx->host_flags, kLanes * sizeof(DevFlags),
+                                hipHostMallocDefault));
         HIP_CHECK(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+        HIP_CHECK(hipStreamCreateWithFlags(&ctx->capture_aux, hipStreamNonBlocking));
+        HIP_CHECK(hipStreamCreateWithFlags(&ctx->aux_stream, hipStreamNonBlocking));
+        HIP_CHECK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+        HIP_CHECK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
         return GS_OK;
     });
     if (rc != GS_OK) {
@@ -666,7 +720,11 @@ int gs_destroy(gs_ctx *ctx)
     (void)hipDeviceSynchronize();
     clear_graphs(ctx);
     for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    if (ctx->capture_aux) (void)hipStreamDestroy(ctx->capture_aux);
+    if (ctx->aux_stream) (void)hipStreamDestroy(ctx->aux_stream);
     if (ctx->host_flags) (void)hipHostFree(ctx->host_flags);
     delete ctx;
     return GS_OK;
@@ -856,10 +914,11 @@ int gs_set_instance_capacity(gs_ctx *ctx, int64_t cap)
         HIP_CHECK(hipSetDevice(ctx->device));
         HIP_CHECK(hipDeviceSynchronize());
         clear_graphs(ctx);
-        for (int i = 0; i < 2; ++i) {
-            ctx->ikeys[i].release();
-            ctx->ivals[i].release();
-        }
+        for (Lane &L : ctx->lanes)
+            for (int i = 0; i < 2; ++i) {
+                L.ikeys[i].release();
+                L.ivals[i].release();
+            }
         ctx->inst_cap = (uint64_t)cap;
         ++ctx->generation;
         return GS_OK;
