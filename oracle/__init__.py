@@ -61,6 +61,10 @@ def lib():
                                  ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp, dp, dp,
                                  dp, dp, i64p, ctypes.c_int64, i32p, dp, i64p, ctypes.c_int]
         L.gso_render.restype = ctypes.c_int
+        L.gso_pixel_trace.argtypes = [fp, fp, fp, fp, fp, ctypes.c_int64, ctypes.c_int, fp, fp,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+        L.gso_pixel_trace.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -165,6 +169,22 @@ def render(scene: dict, pose, intr, width: int, height: int, near: float = 0.2,
     order = np.argsort(vp[:k], kind="stable")
     return Render(rgb, depth, alpha, tfin, dict(zip(COUNTER_NAMES, cnt.tolist())),
                   vp[:k][order], vv[:k][order])
+
+
+def pixel_trace(scene: dict, pose, intr, width: int, height: int, i: int, j: int,
+                near: float = 0.2, eps_alpha: float = DEFAULT_MARGINS[0], cap: int = 256):
+    """Candidates of pixel (i, j) in walk order: rows (g, z, alpha, T before,
+    T after, flags). Diagnostic helper."""
+    m, s, q, o, sh = (_f32(scene[k]) for k in ("means", "scales", "quats", "opacity", "sh"))
+    out = np.zeros((cap, 6))
+    pose = _f32(pose).reshape(12)
+    intr = _f32(intr).reshape(4)
+    fp = ctypes.c_float
+    k = lib().gso_pixel_trace(_ptr(m, fp), _ptr(s, fp), _ptr(q, fp), _ptr(o, fp), _ptr(sh, fp),
+                              len(o), int(scene["sh_degree"]), _ptr(pose, fp), _ptr(intr, fp),
+                              width, height, float(np.float32(near)), eps_alpha, i, j, cap,
+                              _ptr(out, ctypes.c_double))
+    return out[:min(k, cap)]
 
 
 # ------------------------------------------------------------- comparator ----

@@ -399,13 +399,16 @@ static void walk_branching(const cand_t *c, const int *order, int n, int i, doub
     emit_leaf(L, cfg, T, acc);
 }
 
-/* Step 6 with the natural FP64 decisions only. Returns the contributor count. */
+/* Step 6 with the natural FP64 decisions only. Returns the contributor count;
+ * *reach is the number of candidates the walk examined (the stopping one
+ * included). */
 static int walk_plain(const cand_t *c, int n, const walk_cfg_t *cfg, double out[5],
-                      double *T_out, int *marginal)
+                      double *T_out, int *marginal, int *reach)
 {
     double T = 1.0, acc[5] = {0, 0, 0, 0, 0};
     int ncontrib = 0;
     *marginal = 0;
+    *reach = n;
     for (int i = 0; i < n; ++i) {
         const cand_t *k = &c[i];
         if (k->near_marginal) *marginal = 1;
@@ -415,7 +418,10 @@ static int walk_plain(const cand_t *c, int n, const walk_cfg_t *cfg, double out[
         if (a < ALPHA_MIN) continue;
         double Tn = T * (1.0 - a);
         if (fabs(Tn - T_MIN) <= cfg->eps_T * T_MIN) *marginal = 1;
-        if (Tn < T_MIN) break;
+        if (Tn < T_MIN) {
+            *reach = i + 1;
+            break;
+        }
         double w = a * T;
         acc[0] += w * k->rgb[0]; acc[1] += w * k->rgb[1]; acc[2] += w * k->rgb[2];
         acc[3] += w * k->z; acc[4] += w;
@@ -546,22 +552,25 @@ int gso_render(const float *means, const float *scales, const float *quats,
                 int cn = (int)(e - s);
                 int64_t pix = (int64_t)y * W + x;
                 double out[5], T;
-                int marginal;
-                int nc = walk_plain(c, cn, &cfg, out, &T, &marginal);
+                int marginal, reach;
+                int nc = walk_plain(c, cn, &cfg, out, &T, &marginal, &reach);
                 for (int i = 0; i < cn; ++i) n_cand += c[i].in_front && c[i].alpha >= ALPHA_MIN;
                 n_pairs += nc;
                 rgb[pix * 3 + 0] = out[0]; rgb[pix * 3 + 1] = out[1]; rgb[pix * 3 + 2] = out[2];
                 depth[pix] = out[3]; alpha[pix] = out[4]; tfinal[pix] = T;
-                /* depth near-ties between neighbours in the (z, index) order */
+                /* depth near-ties between neighbours in the (z, index) order, among
+                 * the candidates the walk reaches: past the stop, any reordering
+                 * changes the pixel by less than the final transmittance (< 1e-4
+                 * times the largest colour). */
                 int ties[8], nt = 0;
-                for (int i = 0; i + 1 < cn; ++i)
+                for (int i = 0; i + 1 < cn && i < reach; ++i)
                     if (fabs(c[i + 1].z - c[i].z) <= eps_z) {
                         if (nt < 8) ties[nt] = i;
                         ++nt;
                     }
                 if (!marginal && nt == 0) { s = e; continue; }
                 ++n_flag;
-                if (nt > 4) { ++n_unres; s = e; continue; }
+                if (nt > 6) { ++n_unres; s = e; continue; }
                 if (cn > order_cap) {
                     order_cap = cn * 2;
                     order = (int *)realloc(order, sizeof(int) * order_cap);
@@ -599,4 +608,50 @@ int gso_render(const float *means, const float *scales, const float *quats,
     *n_var = var_count;
     free(P); free(pb); free(live); free(row_start); free(row_g); free(fill);
     return 0;
+}
+
+/*
+ * Diagnostic: the (z, index)-ordered candidates of one pixel (i, j) with
+ * alpha >= ALPHA_MIN (1 - eps_alpha), for inspecting decisions near a
+ * threshold. out[k*6 ...] = g, z, alpha, T before, T after, flags (1 near
+ * marginal, 2 not in front). Returns the number of candidates (at most cap
+ * are written).
+ */
+int gso_pixel_trace(const float *means, const float *scales, const float *quats,
+                    const float *opacity, const float *sh, int64_t n, int deg,
+                    const float pose[12], const float intr[4], int W, int H, double near,
+                    double eps_alpha, int i, int j, int cap, double *out)
+{
+    camera_t cam;
+    camera_setup(pose, intr, W, H, &cam);
+    int ncoef = (deg + 1) * (deg + 1);
+    int m = 0, mcap = 1024;
+    cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * mcap);
+    for (int64_t g = 0; g < n; ++g) {
+        proj_t P;
+        if (!project_one(&cam, means + g * 3, scales + g * 3, quats + g * 4, opacity[g],
+                         sh + g * ncoef * 3, deg, near, 1e-5, &P))
+            continue;
+        double dx = i + 0.5 - P.u, dy = j + 0.5 - P.v;
+        double power = -0.5 * (P.conic[0] * dx * dx + 2.0 * P.conic[1] * dx * dy +
+                               P.conic[2] * dy * dy);
+        double a = fmin(ALPHA_MAX, P.o * exp(power));
+        if (a < ALPHA_MIN * (1.0 - eps_alpha)) continue;
+        if (m == mcap) { mcap *= 2; buf = (cand_t *)realloc(buf, sizeof(cand_t) * mcap); }
+        cand_t *c = &buf[m++];
+        c->x = i; c->g = (int32_t)g; c->z = P.z; c->alpha = a;
+        c->rgb[0] = P.rgb[0]; c->rgb[1] = P.rgb[1]; c->rgb[2] = P.rgb[2];
+        c->near_marginal = P.near_marginal; c->in_front = P.in_front;
+    }
+    qsort(buf, m, sizeof(cand_t), cand_cmp);
+    double T = 1.0;
+    for (int k = 0; k < m && k < cap; ++k) {
+        double Tn = T * (1.0 - buf[k].alpha);
+        out[k * 6 + 0] = buf[k].g; out[k * 6 + 1] = buf[k].z; out[k * 6 + 2] = buf[k].alpha;
+        out[k * 6 + 3] = T; out[k * 6 + 4] = Tn;
+        out[k * 6 + 5] = buf[k].near_marginal + 2 * !buf[k].in_front;
+        if (buf[k].in_front && buf[k].alpha >= ALPHA_MIN && !(Tn < T_MIN)) T = Tn;
+    }
+    free(buf);
+    return m;
 }

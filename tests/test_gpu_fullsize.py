@@ -1,0 +1,87 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times (batched, two streams, HIP-graph replay): every camera of the batch is
+rendered, a seeded sample of cameras is compared with the FP64 oracle
+(max-abs RGB 2e-3, relative depth 1e-3, max-abs alpha 2e-3 with the
+comparator's alternatives), and whole-batch properties are checked on every
+camera (finite values, alpha in [0, 1 - 1e-4], depth 0 exactly where alpha is
+0, colour bounded by alpha times the largest scene colour)."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+
+pytestmark = pytest.mark.gpu
+
+
+def _props(rgb, depth, alpha):
+    import torch
+    assert bool(torch.isfinite(rgb).all()) and bool(torch.isfinite(depth).all())
+    assert float(alpha.min()) >= 0.0 and float(alpha.max()) <= 1.0 - 1e-4 + 1e-6
+    zero = alpha == 0
+    assert bool((depth[zero] == 0).all())
+    assert bool((depth[~zero] > 0.2 - 1e-6).all())
+
+
+def _run(gpu_renderer, k, step, n_sample, seed):
+    import torch
+    w = scenegen.workload(k)
+    scenes = [scenegen.make_scene(k, s) for s in range(w.n_scenes)]
+    cams = scenegen.make_cameras(k, step=step)
+    sids = [gpu_renderer.upload_scene(s) for s in scenes]
+    ids = np.array([sids[i] for i in cams["scene_ids"]], np.int32)
+    P = torch.as_tensor(cams["poses"]).cuda()
+    K = torch.as_tensor(cams["intrinsics"]).cuda()
+    W, H = cams["width"], cams["height"]
+    out = gpu_renderer.alloc_outputs(len(ids), W, H)
+    for _ in range(2):   # capture, then replay
+        gpu_renderer.render(ids, P, K, W, H, out=out, use_graph=True)
+    torch.cuda.synchronize()
+    rgb, depth, alpha = out
+    _props(rgb, depth, alpha)
+    pick = scenegen.camera_subset(k, n_sample, seed=seed)
+    fails = 0
+    for c in pick:
+        ref = oracle.render(scenes[int(cams["scene_ids"][c])], cams["poses"][c],
+                            cams["intrinsics"][c], W, H)
+        rep = oracle.compare(ref, rgb[c].cpu().numpy(), depth[c].cpu().numpy(),
+                             alpha[c].cpu().numpy())
+        print(f"w{k} step {step} cam {c}: max|rgb| {rep['max_abs_rgb']:.2e} rel depth "
+              f"{rep['max_rel_depth']:.2e} rescued {rep['rescued']} failed {rep['failed']}",
+              flush=True)
+        fails += rep["failed"]
+    st = gpu_renderer.stats()
+    gpu_renderer.drop_graphs()
+    for s in sids:
+        gpu_renderer.release_scene(s)
+    assert fails == 0
+    return st
+
+
+def test_workload2_all_4096_cameras_sampled_parity(gpu_renderer):
+    st = _run(gpu_renderer, 2, 0, 12, seed=5)
+    assert st["visible"] > 0 and st["regrows"] == 0
+
+
+def test_workload4_stress_step_sampled_parity(gpu_renderer):
+    _run(gpu_renderer, 4, 37, 8, seed=9)
+
+
+def test_autotuner_choice_is_used_and_bitwise_identical(gpu_renderer):
+    import torch
+    sc = scenegen.make_scene(1)
+    cams = scenegen.make_cameras(1)
+    sid = gpu_renderer.upload_scene(sc)
+    ids = [sid] * 32
+    P, K = cams["poses"][:32], cams["intrinsics"][:32]
+    base = [t.cpu().numpy() for t in gpu_renderer.render(ids, P, K, 640, 480, tile=(16, 16),
+                                                         lds_batch=256, persistent=0)]
+    gpu_renderer.autotune(ids, P, K, 640, 480)
+    got = gpu_renderer.render(ids, P, K, 640, 480)
+    st = gpu_renderer.stats()
+    print("autotuned", {k: st[k] for k in ("tile_w", "tile_h", "lds_batch", "chunk_cams",
+                                             "persistent")})
+    for x, y in zip(base, got):
+        assert np.array_equal(x, y.cpu().numpy())
+    torch.cuda.synchronize()
+    gpu_renderer.release_scene(sid)

@@ -211,3 +211,31 @@ def test_two_saturated_alternative_is_listed():
     assert c1 > 0.99
     rep = oracle.compare(r, rgb, dep, alp)
     assert rep["failed"] == 0 and rep["rescued"] >= 1
+
+
+def test_near_tie_before_stop_listed_despite_ties_after_stop():
+    # Two contributors one FP32 ulp apart in depth early in the walk, then
+    # opaque Gaussians that stop it, then many tied pairs past the stop. The
+    # swapped order of the first pair must be listed as an alternative.
+    Y00 = 1.0 / (2.0 * math.sqrt(math.pi))
+    z1 = 2.0
+    z2 = float(np.nextafter(np.float32(2.0), np.float32(3.0)))
+    zs = [z1, z2, 3.0, 3.1, 3.2]
+    zs += [z for k in range(8) for z in (5.0 + k, float(np.nextafter(np.float32(5.0 + k),
+                                                                      np.float32(99))))]
+    n = len(zs)
+    cols = np.full((n, 3), 0.5)
+    cols[0] = (1.0, 0.0, 0.0)
+    cols[1] = (0.0, 0.0, 1.0)
+    op = np.full(n, 0.999, np.float32)
+    op[0], op[1] = 0.5, 0.6
+    sc = dict(means=np.array([[0.0, 0.0, z] for z in zs], np.float32),
+              scales=np.full((n, 3), 0.3, np.float32),
+              quats=np.tile(np.array([1, 0, 0, 0], np.float32), (n, 1)), opacity=op,
+              sh=((cols - 0.5) / Y00).astype(np.float32).reshape(n, 1, 3), sh_degree=0)
+    r = oracle.render(sc, IDENT_POSE, [50, 50, 32.5, 24.5], 64, 48)
+    p = 24 * 64 + 32
+    rows = r.var_vals[r.var_pix == p]
+    assert len(rows) >= 2
+    # one alternative puts the blue Gaussian first: more blue than the primary
+    assert any(v[2] - r.rgb[24, 32, 2] > 1e-2 for v in rows)
