@@ -197,6 +197,79 @@ int gs_autotune(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
                 const float *intrinsics, int32_t width, int32_t height, float *rgb, float *depth,
                 const char *cache_path, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned 4x upsampler (a workload of this renderer, not part of the paper):
+ * render at W/4 x H/4 with intrinsics / 4, then four 3x3 convolutions
+ * (4 -> 32 -> 32 -> 32 -> 64 channels, ReLU after the first three; BF16
+ * weights and activations on MFMA, FP32 accumulation), 4x pixel shuffle plus
+ * bilinear 4x upsampling of the low-resolution RGB + depth/10.
+ *
+ * Parameter vector (FP32, `gs_upsampler_num_params()` values), per layer
+ * l = 1..4: weights [cout][3][3][cin] then bias [cout], with
+ * (cin, cout) = (4, 32), (32, 32), (32, 32), (32, 64).
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t batch;   /* cameras per optimisation step (default 32) */
+    int32_t steps;   /* optimisation steps */
+    float lr;        /* Adam learning rate at step 0 (default 1e-3) */
+    float lr_min;    /* cosine-decayed to this value at the last step */
+    int32_t reserved[4];
+} gs_train_opts;
+
+/* Number of FP32 values of the parameter vector. */
+int64_t gs_upsampler_num_params(void);
+
+/* He-uniform weights from `seed`, zero biases, last layer zero (so the
+ * untrained network equals bilinear upsampling); resets the Adam state. */
+int gs_upsampler_init(gs_ctx *ctx, uint64_t seed);
+
+/* Copy the parameter vector in (host, n values) or out. Setting resets Adam. */
+int gs_upsampler_set_weights(gs_ctx *ctx, const float *params, int64_t n);
+int gs_upsampler_get_weights(gs_ctx *ctx, float *params, int64_t n);
+
+/* Network forward on given low-res frames.
+ *   rgb_lo [n][h][w][3], depth_lo [n][h][w] DEVICE; outputs rgb_out
+ *   [n][4h][4w][3], depth_out [n][4h][4w] DEVICE. Asynchronous on stream. */
+int gs_upsampler_forward(gs_ctx *ctx, int32_t n, int32_t h, int32_t w, const float *rgb_lo,
+                         const float *depth_lo, float *rgb_out, float *depth_out, void *stream);
+
+/* Forward + backward for the loss mean_p sum_c w_c (pred_c - target_c)^2,
+ * w = (1, 1, 1, 0.1) over (r, g, b, depth/10), targets rgb_hi [n][4h][4w][3]
+ * and depth_hi [n][4h][4w] (DEVICE). Writes the loss and the gradient of the
+ * parameter vector to HOST memory. Synchronous. No parameter update. */
+int gs_upsampler_grads(gs_ctx *ctx, int32_t n, int32_t h, int32_t w, const float *rgb_lo,
+                       const float *depth_lo, const float *rgb_hi, const float *depth_hi,
+                       float *loss_out, float *grads_out, void *stream);
+
+/* Train on n_pairs cameras (scene_ids HOST, poses / full-res intrinsics
+ * DEVICE): every step renders `batch` cameras at width x height (targets)
+ * and at width/4 x height/4 (inputs) with the batched renderer, runs the
+ * network forward and backward and applies Adam; cameras are taken in order,
+ * wrapping around. loss_curve (HOST, `steps` values, nullable) receives each
+ * step's loss. Synchronous. */
+int gs_upsampler_train(gs_ctx *ctx, const gs_train_opts *opts, int32_t n_pairs,
+                       const int32_t *scene_ids, const float *poses, const float *intrinsics,
+                       int32_t width, int32_t height, float *loss_curve, void *stream);
+
+/* Upsampled render: the batch is rendered at width/4 x height/4 (intrinsics
+ * given for the full resolution), upsampled by the network, and every camera
+ * whose confidence score (mean squared neighbour difference of its low-res
+ * RGB + depth/10) exceeds fallback_threshold is rendered again at full
+ * resolution into the same output slots. score_out (DEVICE [n], nullable)
+ * receives the scores, *n_fallback_out (HOST, nullable) the number of
+ * re-rendered cameras. width and height must be multiples of 4. */
+int gs_render_batch_upsampled(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids,
+                              const float *poses, const float *intrinsics, int32_t width,
+                              int32_t height, float *rgb, float *depth, float *score_out,
+                              float fallback_threshold, int32_t *n_fallback_out,
+                              const gs_render_opts *opts, void *stream);
+
+/* Per-frame PSNR in dB of RGB clamped to [0, 1]: a, b DEVICE [n][npix][3],
+ * out DEVICE [n]. Asynchronous. */
+int gs_frame_psnr(gs_ctx *ctx, int32_t n, int64_t npix, const float *a, const float *b,
+                  float *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

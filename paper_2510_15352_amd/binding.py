@@ -24,7 +24,10 @@ GS_MODE_PLAIN, GS_MODE_BATCHED = 0, 1
 # every symbol include/gs.h declares
 EXPORTS = ("gs_abi_sizes", "gs_default_opts", "gs_create", "gs_destroy", "gs_last_error", "gs_upload_scene",
            "gs_release_scene", "gs_scene_size", "gs_render_batch", "gs_last_stats",
-           "gs_debug_project", "gs_autotune", "gs_set_instance_capacity", "gs_clear_graphs")
+           "gs_debug_project", "gs_autotune", "gs_set_instance_capacity", "gs_clear_graphs",
+           "gs_upsampler_num_params", "gs_upsampler_init", "gs_upsampler_set_weights",
+           "gs_upsampler_get_weights", "gs_upsampler_forward", "gs_upsampler_grads",
+           "gs_upsampler_train", "gs_render_batch_upsampled", "gs_frame_psnr")
 
 
 class GsError(RuntimeError):
@@ -46,6 +49,11 @@ class RenderOpts(ctypes.Structure):
                 ("persistent", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("count_pairs", ctypes.c_int32),
                 ("streams", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("steps", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("lr_min", ctypes.c_float), ("reserved", ctypes.c_int32 * 4)]
+
 
 STAGES = ("setup", "project", "compact", "depth_sort", "emit", "tile_sort", "ranges", "raster")
 
@@ -90,6 +98,18 @@ def load():
     L.gs_autotune.argtypes = [vp, i32, vp, vp, vp, i32, i32, vp, vp, ctypes.c_char_p, vp]
     L.gs_set_instance_capacity.argtypes = [vp, i64]
     L.gs_clear_graphs.argtypes = [vp]
+    L.gs_upsampler_num_params.argtypes = []
+    L.gs_upsampler_num_params.restype = i64
+    L.gs_upsampler_init.argtypes = [vp, ctypes.c_uint64]
+    L.gs_upsampler_set_weights.argtypes = [vp, vp, i64]
+    L.gs_upsampler_get_weights.argtypes = [vp, vp, i64]
+    L.gs_upsampler_forward.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
+    L.gs_upsampler_grads.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.gs_upsampler_train.argtypes = [vp, ctypes.POINTER(TrainOpts), i32, vp, vp, vp, i32, i32, vp,
+                                     vp]
+    L.gs_render_batch_upsampled.argtypes = [vp, i32, vp, vp, vp, i32, i32, vp, vp, vp,
+                                            ctypes.c_float, vp, ctypes.POINTER(RenderOpts), vp]
+    L.gs_frame_psnr.argtypes = [vp, i32, i64, vp, vp, vp, vp]
     for name in EXPORTS:
         if not hasattr(L, name):
             raise RuntimeError(f"{LIB_PATH} does not export {name}")
@@ -250,6 +270,87 @@ class Renderer:
                                               int(width), int(height), float(near),
                                               out.data_ptr()))
         return out.cpu().numpy()
+
+    # --------------------------------------------------------- upsampler --
+    def up_num_params(self) -> int:
+        return int(self.lib.gs_upsampler_num_params())
+
+    def up_init(self, seed: int = 0):
+        self._check(self.lib.gs_upsampler_init(self.ctx, int(seed)))
+
+    def up_set(self, params):
+        p = np.ascontiguousarray(np.asarray(params, np.float32).reshape(-1))
+        self._check(self.lib.gs_upsampler_set_weights(self.ctx, p.ctypes.data, len(p)))
+
+    def up_get(self):
+        p = np.zeros(self.up_num_params(), np.float32)
+        self._check(self.lib.gs_upsampler_get_weights(self.ctx, p.ctypes.data, len(p)))
+        return p
+
+    def up_forward(self, rgb_lo, depth_lo):
+        torch = self.torch
+        n, h, w, _ = rgb_lo.shape
+        rgb = torch.empty((n, 4 * h, 4 * w, 3), dtype=torch.float32, device=self.device)
+        depth = torch.empty((n, 4 * h, 4 * w), dtype=torch.float32, device=self.device)
+        a, d = rgb_lo.contiguous(), depth_lo.contiguous()
+        self._check(self.lib.gs_upsampler_forward(self.ctx, n, h, w, a.data_ptr(), d.data_ptr(),
+                                                  rgb.data_ptr(), depth.data_ptr(),
+                                                  _stream_ptr(torch)))
+        return rgb, depth
+
+    def up_grads(self, rgb_lo, depth_lo, rgb_hi, depth_hi):
+        n, h, w, _ = rgb_lo.shape
+        tensors = [t.contiguous() for t in (rgb_lo, depth_lo, rgb_hi, depth_hi)]
+        loss = ctypes.c_float()
+        g = np.zeros(self.up_num_params(), np.float32)
+        self._check(self.lib.gs_upsampler_grads(self.ctx, n, h, w,
+                                                *[t.data_ptr() for t in tensors],
+                                                ctypes.byref(loss), g.ctypes.data,
+                                                _stream_ptr(self.torch)))
+        return float(loss.value), g
+
+    def up_train(self, scene_ids, poses, intrinsics, width, height, batch=32, steps=100, lr=1e-3,
+                 lr_min=0.0):
+        torch = self.torch
+        sids = np.ascontiguousarray(np.asarray(scene_ids, dtype=np.int32).reshape(-1))
+        P = _dev_f32(torch, poses, self.device)
+        K = _dev_f32(torch, intrinsics, self.device)
+        o = TrainOpts(int(batch), int(steps), float(lr), float(lr_min))
+        curve = np.zeros(int(steps), np.float32)
+        self._check(self.lib.gs_upsampler_train(self.ctx, ctypes.byref(o), len(sids),
+                                                sids.ctypes.data, P.data_ptr(), K.data_ptr(),
+                                                int(width), int(height), curve.ctypes.data,
+                                                _stream_ptr(torch)))
+        return curve
+
+    def render_upsampled(self, scene_ids, poses, intrinsics, width, height, threshold=float("inf"),
+                         out=None, opts=None, **kw):
+        """Upsampled render; returns (rgb, depth, score, n_fallback)."""
+        torch = self.torch
+        sids = np.ascontiguousarray(np.asarray(scene_ids, dtype=np.int32).reshape(-1))
+        n = len(sids)
+        P = poses if (torch.is_tensor(poses) and poses.is_cuda) else _dev_f32(torch, poses, self.device)
+        K = intrinsics if (torch.is_tensor(intrinsics) and intrinsics.is_cuda) \
+            else _dev_f32(torch, intrinsics, self.device)
+        rgb, depth, _ = out if out is not None else self.alloc_outputs(n, width, height, alpha=False)
+        score = torch.empty(n, dtype=torch.float32, device=self.device)
+        nf = ctypes.c_int32()
+        o = opts if opts is not None else self.opts(**kw)
+        self._check(self.lib.gs_render_batch_upsampled(
+            self.ctx, n, sids.ctypes.data, P.data_ptr(), K.data_ptr(), int(width), int(height),
+            rgb.data_ptr(), depth.data_ptr(), score.data_ptr(), float(threshold), ctypes.byref(nf),
+            ctypes.byref(o), _stream_ptr(torch)))
+        return rgb, depth, score, int(nf.value)
+
+    def frame_psnr(self, a, b):
+        torch = self.torch
+        n = a.shape[0]
+        npix = a[0].numel() // 3
+        out = torch.empty(n, dtype=torch.float32, device=self.device)
+        self._check(self.lib.gs_frame_psnr(self.ctx, n, npix, a.contiguous().data_ptr(),
+                                           b.contiguous().data_ptr(), out.data_ptr(),
+                                           _stream_ptr(torch)))
+        return out
 
     def autotune(self, scene_ids, poses, intrinsics, width, height, cache_path=None):
         torch = self.torch

@@ -17,6 +17,7 @@
 #include "../../include/gs.h"
 #include "gs_device.h"
 #include "kernels.h"
+#include "up_kernels.h"
 
 using namespace gs;
 
@@ -117,6 +118,28 @@ struct Lane {
 
 constexpr int kLanes = 2;
 
+// Learned upsampler: FP32 master weights [cout][9][32] (layer 1's four input
+// channels zero-padded to 32), Adam moments, BF16 packed copies, buffers.
+constexpr int kUpCin[4] = {4, 32, 32, 32};
+constexpr int kUpCout[4] = {32, 32, 32, 64};
+constexpr int kUpCinM = 32;
+constexpr int kUpChunk = 512;  // cameras per network pass of an upsampled render
+
+struct Upsampler {
+    bool ready = false;
+    bool packed = false;
+    int step = 0;
+    DevBuf<float> w[4], b[4], mw[4], vw[4], mb[4], vb[4], gw[4], gb[4];
+    DevBuf<uint16_t> wf[4], wd[4];
+    // activations of up to `cap` images of h x w
+    DevBuf<float> x0f, y4, lpart, wpart, bpart, scalar;
+    DevBuf<uint16_t> x0b, a1, a2, a3, dy4, da3, da2, da1;
+    // renders used by training and the upsampled form
+    DevBuf<float> lo_rgb, lo_depth, hi_rgb, hi_depth, intr_lo, score, fb_rgb, fb_depth, fb_poses,
+        fb_intr;
+    DevBuf<int32_t> fb_list;
+};
+
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -148,6 +171,7 @@ struct gs_ctx {
     hipStream_t aux_stream = nullptr;   // second stream of an eager render
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
+    Upsampler up;
     std::vector<hipEvent_t> events;  // pool for stage timing
     std::map<std::string, std::unique_ptr<GraphEntry>> graphs;
     std::map<std::string, Choice> tuned;
@@ -661,6 +685,179 @@ int validate_render_args(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, 
 
 }  // namespace
 
+
+namespace {
+
+// ------------------------------------------------------------- upsampler --
+
+int64_t up_num_params()
+{
+    int64_t n = 0;
+    for (int l = 0; l < 4; ++l) n += (int64_t)kUpCout[l] * 9 * kUpCin[l] + kUpCout[l];
+    return n;
+}
+
+void up_zero_state(gs_ctx *ctx)
+{
+    Upsampler &U = ctx->up;
+    for (int l = 0; l < 4; ++l) {
+        const size_t nw = (size_t)kUpCout[l] * 9 * kUpCinM, nb = kUpCout[l];
+        U.w[l].reserve(nw);
+        U.b[l].reserve(nb);
+        U.mw[l].reserve(nw);
+        U.vw[l].reserve(nw);
+        U.mb[l].reserve(nb);
+        U.vb[l].reserve(nb);
+        U.gw[l].reserve(nw);
+        U.gb[l].reserve(nb);
+        U.wf[l].reserve((size_t)9 * kUpCout[l] * kUpCinM);
+        U.wd[l].reserve((size_t)9 * kUpCout[l] * kUpCinM);
+        HIP_CHECK(hipMemset(U.mw[l].p, 0, nw * 4));
+        HIP_CHECK(hipMemset(U.vw[l].p, 0, nw * 4));
+        HIP_CHECK(hipMemset(U.mb[l].p, 0, nb * 4));
+        HIP_CHECK(hipMemset(U.vb[l].p, 0, nb * 4));
+    }
+    U.step = 0;
+    U.packed = false;
+}
+
+// Parameter vector (oracle layout) -> FP32 master weights.
+void up_set(gs_ctx *ctx, const float *params)
+{
+    Upsampler &U = ctx->up;
+    up_zero_state(ctx);
+    const float *src = params;
+    for (int l = 0; l < 4; ++l) {
+        const int ci = kUpCin[l], co = kUpCout[l];
+        std::vector<float> w((size_t)co * 9 * kUpCinM, 0.0f);
+        for (int o = 0; o < co; ++o)
+            for (int t = 0; t < 9; ++t)
+                for (int c = 0; c < ci; ++c) w[((size_t)o * 9 + t) * kUpCinM + c] = src[((size_t)o * 9 + t) * ci + c];
+        src += (size_t)co * 9 * ci;
+        HIP_CHECK(hipMemcpy(U.w[l].p, w.data(), w.size() * 4, hipMemcpyHostToDevice));
+        HIP_CHECK(hipMemcpy(U.b[l].p, src, (size_t)co * 4, hipMemcpyHostToDevice));
+        src += co;
+    }
+    U.ready = true;
+}
+
+// FP32 master tensors (weights or their gradients) -> oracle layout.
+void up_get(gs_ctx *ctx, DevBuf<float> *wsrc, DevBuf<float> *bsrc, float *params)
+{
+    float *dst = params;
+    for (int l = 0; l < 4; ++l) {
+        const int ci = kUpCin[l], co = kUpCout[l];
+        std::vector<float> w((size_t)co * 9 * kUpCinM);
+        HIP_CHECK(hipMemcpy(w.data(), wsrc[l].p, w.size() * 4, hipMemcpyDeviceToHost));
+        for (int o = 0; o < co; ++o)
+            for (int t = 0; t < 9; ++t)
+                for (int c = 0; c < ci; ++c) dst[((size_t)o * 9 + t) * ci + c] = w[((size_t)o * 9 + t) * kUpCinM + c];
+        dst += (size_t)co * 9 * ci;
+        HIP_CHECK(hipMemcpy(dst, bsrc[l].p, (size_t)co * 4, hipMemcpyDeviceToHost));
+        dst += co;
+    }
+}
+
+void up_pack(gs_ctx *ctx, hipStream_t st)
+{
+    Upsampler &U = ctx->up;
+    for (int l = 0; l < 4; ++l)
+        launch_pack_weights(U.w[l].p, kUpCout[l], kUpCinM, kUpCinM, U.wf[l].p,
+                            l > 0 ? U.wd[l].p : nullptr, st);
+    U.packed = true;
+}
+
+void up_alloc(gs_ctx *ctx, int n, int h, int w, bool train)
+{
+    Upsampler &U = ctx->up;
+    const size_t px = (size_t)n * h * w;
+    U.x0f.reserve(px * 4);
+    U.x0b.reserve(px * 32);
+    U.a1.reserve(px * 32);
+    U.a2.reserve(px * 32);
+    U.a3.reserve(px * 32);
+    U.y4.reserve(px * 64);
+    U.scalar.reserve(4);
+    if (train) {
+        U.dy4.reserve(px * 64);
+        U.da3.reserve(px * 32);
+        U.da2.reserve(px * 32);
+        U.da1.reserve(px * 32);
+        U.lpart.reserve((size_t)up_head_blocks(n, h, w));
+        U.wpart.reserve((size_t)up_conv_blocks(n, h, w) * 64 * 9 * 32);
+        U.bpart.reserve((size_t)up_conv_blocks(n, h, w) * 64);
+    }
+}
+
+// x0b / x0f of n images must be filled; writes y4.
+void up_forward(gs_ctx *ctx, int n, int h, int w, hipStream_t st)
+{
+    Upsampler &U = ctx->up;
+    launch_up_conv(32, 32, UP_EPI_RELU_BF16, U.x0b.p, U.wf[0].p, U.b[0].p, n, h, w, nullptr, U.a1.p, st);
+    launch_up_conv(32, 32, UP_EPI_RELU_BF16, U.a1.p, U.wf[1].p, U.b[1].p, n, h, w, nullptr, U.a2.p, st);
+    launch_up_conv(32, 32, UP_EPI_RELU_BF16, U.a2.p, U.wf[2].p, U.b[2].p, n, h, w, nullptr, U.a3.p, st);
+    launch_up_conv(32, 64, UP_EPI_F32, U.a3.p, U.wf[3].p, U.b[3].p, n, h, w, nullptr, U.y4.p, st);
+}
+
+// dy4 must be filled (training head); writes gw / gb of every layer.
+void up_backward(gs_ctx *ctx, int n, int h, int w, hipStream_t st)
+{
+    Upsampler &U = ctx->up;
+    const int nblk = up_conv_blocks(n, h, w);
+    const uint16_t *xin[4] = {U.x0b.p, U.a1.p, U.a2.p, U.a3.p};
+    uint16_t *dout[4] = {U.da1.p, U.da2.p, U.da3.p, U.dy4.p};  // dL/d(output of layer l)
+    for (int l = 3; l >= 0; --l) {
+        const int co = kUpCout[l];
+        launch_up_wgrad(kUpCinM, co, xin[l], dout[l], n, h, w, U.wpart.p, U.bpart.p, st);
+        launch_sum_partials(U.wpart.p, nblk, co * 9 * kUpCinM, U.gw[l].p, st);
+        launch_sum_partials(U.bpart.p, nblk, co, U.gb[l].p, st);
+        if (l > 0)  // dL/d(input of layer l), masked by ReLU'(previous output)
+            launch_up_conv(co, kUpCinM, UP_EPI_MASK_BF16, dout[l], U.wd[l].p, nullptr, n, h, w,
+                           xin[l], dout[l - 1], st);
+    }
+}
+
+float up_loss_and_grads(gs_ctx *ctx, int n, int h, int w, const float *rgb_lo,
+                        const float *depth_lo, const float *rgb_hi, const float *depth_hi,
+                        hipStream_t st)
+{
+    Upsampler &U = ctx->up;
+    up_alloc(ctx, n, h, w, true);
+    if (!U.packed) up_pack(ctx, st);
+    launch_up_input(rgb_lo, depth_lo, (int64_t)n * h * w, U.x0f.p, U.x0b.p, st);
+    up_forward(ctx, n, h, w, st);
+    launch_up_head(true, U.x0f.p, U.y4.p, h, w, n, nullptr, nullptr, rgb_hi, depth_hi, U.lpart.p,
+                   U.dy4.p, st);
+    up_backward(ctx, n, h, w, st);
+    const int nb = up_head_blocks(n, h, w);
+    launch_sum_partials(U.lpart.p, nb, 1, U.scalar.p, st);
+    float loss = 0.0f;
+    HIP_CHECK(hipMemcpyAsync(&loss, U.scalar.p, 4, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    return loss / (float)((int64_t)n * h * w * 16);
+}
+
+void up_adam(gs_ctx *ctx, float lr, hipStream_t st)
+{
+    Upsampler &U = ctx->up;
+    ++U.step;
+    for (int l = 0; l < 4; ++l) {
+        launch_adam(U.w[l].p, U.mw[l].p, U.vw[l].p, U.gw[l].p, kUpCout[l] * 9 * kUpCinM, lr, U.step, st);
+        launch_adam(U.b[l].p, U.mb[l].p, U.vb[l].p, U.gb[l].p, kUpCout[l], lr, U.step, st);
+    }
+    U.packed = false;
+}
+
+uint64_t splitmix(uint64_t &x)
+{
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+}  // namespace
+
 extern "C" {
 
 int gs_abi_sizes(int32_t *scene_desc, int32_t *render_opts, int32_t *stats)
@@ -1063,6 +1260,246 @@ int gs_autotune(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
                 fclose(f);
             }
         }
+        return GS_OK;
+    });
+}
+
+int64_t gs_upsampler_num_params(void) { return up_num_params(); }
+
+int gs_upsampler_init(gs_ctx *ctx, uint64_t seed)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        std::vector<float> p((size_t)up_num_params(), 0.0f);
+        uint64_t st = seed * 0x2545F4914F6CDD1Dull + 1;
+        float *dst = p.data();
+        for (int l = 0; l < 4; ++l) {
+            const int ci = kUpCin[l], co = kUpCout[l];
+            const double bound = std::sqrt(6.0 / (9.0 * ci));
+            for (size_t i = 0; i < (size_t)co * 9 * ci; ++i) {
+                const double u = (double)(splitmix(st) >> 11) * (1.0 / 9007199254740992.0);
+                dst[i] = l == 3 ? 0.0f : (float)((2.0 * u - 1.0) * bound);
+            }
+            dst += (size_t)co * 9 * ci + co;  // biases stay zero
+        }
+        up_set(ctx, p.data());
+        return GS_OK;
+    });
+}
+
+int gs_upsampler_set_weights(gs_ctx *ctx, const float *params, int64_t n)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (!params || n != up_num_params())
+        return fail(ctx, GS_ERR_INVALID_ARG, "parameter vector must hold gs_upsampler_num_params() values");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        up_set(ctx, params);
+        return GS_OK;
+    });
+}
+
+int gs_upsampler_get_weights(gs_ctx *ctx, float *params, int64_t n)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (!params || n != up_num_params())
+        return fail(ctx, GS_ERR_INVALID_ARG, "parameter vector must hold gs_upsampler_num_params() values");
+    if (!ctx->up.ready) return fail(ctx, GS_ERR_NOT_TRAINED, "upsampler not initialised");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        HIP_CHECK(hipDeviceSynchronize());
+        up_get(ctx, ctx->up.w, ctx->up.b, params);
+        return GS_OK;
+    });
+}
+
+int gs_upsampler_forward(gs_ctx *ctx, int32_t n, int32_t h, int32_t w, const float *rgb_lo,
+                         const float *depth_lo, float *rgb_out, float *depth_out, void *stream)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (n < 1 || h < 1 || w < 1 || !rgb_lo || !depth_lo || !rgb_out || !depth_out)
+        return fail(ctx, GS_ERR_INVALID_ARG, "bad upsampler forward arguments");
+    if (!ctx->up.ready) return fail(ctx, GS_ERR_NOT_TRAINED, "upsampler not initialised");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        hipStream_t st = (hipStream_t)stream;
+        Upsampler &U = ctx->up;
+        if (!U.packed) up_pack(ctx, st);
+        for (int c0 = 0; c0 < n; c0 += kUpChunk) {
+            const int m = std::min(kUpChunk, n - c0);
+            up_alloc(ctx, m, h, w, false);
+            const int64_t lp = (int64_t)h * w, hp = lp * 16;
+            launch_up_input(rgb_lo + c0 * lp * 3, depth_lo + c0 * lp, m * lp, U.x0f.p, U.x0b.p, st);
+            up_forward(ctx, m, h, w, st);
+            launch_up_head(false, U.x0f.p, U.y4.p, h, w, m, rgb_out + c0 * hp * 3,
+                           depth_out + c0 * hp, nullptr, nullptr, nullptr, nullptr, st);
+        }
+        HIP_CHECK(hipGetLastError());
+        return GS_OK;
+    });
+}
+
+int gs_upsampler_grads(gs_ctx *ctx, int32_t n, int32_t h, int32_t w, const float *rgb_lo,
+                       const float *depth_lo, const float *rgb_hi, const float *depth_hi,
+                       float *loss_out, float *grads_out, void *stream)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (n < 1 || h < 1 || w < 1 || !rgb_lo || !depth_lo || !rgb_hi || !depth_hi)
+        return fail(ctx, GS_ERR_INVALID_ARG, "bad upsampler gradient arguments");
+    if (!ctx->up.ready) return fail(ctx, GS_ERR_NOT_TRAINED, "upsampler not initialised");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        hipStream_t st = (hipStream_t)stream;
+        const float loss = up_loss_and_grads(ctx, n, h, w, rgb_lo, depth_lo, rgb_hi, depth_hi, st);
+        if (loss_out) *loss_out = loss;
+        if (grads_out) up_get(ctx, ctx->up.gw, ctx->up.gb, grads_out);
+        return GS_OK;
+    });
+}
+
+int gs_upsampler_train(gs_ctx *ctx, const gs_train_opts *opts, int32_t n_pairs,
+                       const int32_t *scene_ids, const float *poses, const float *intrinsics,
+                       int32_t width, int32_t height, float *loss_curve, void *stream)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (!opts || !scene_ids || !poses || !intrinsics || n_pairs < 1 || width % 4 || height % 4 ||
+        width < 4 || height < 4)
+        return fail(ctx, GS_ERR_INVALID_ARG, "bad training arguments (sizes must be multiples of 4)");
+    if (!ctx->up.ready) return fail(ctx, GS_ERR_NOT_TRAINED, "upsampler not initialised");
+    const int batch = opts->batch > 0 ? opts->batch : 32;
+    if (batch > n_pairs) return fail(ctx, GS_ERR_INVALID_ARG, "batch larger than the camera set");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        hipStream_t st = (hipStream_t)stream;
+        Upsampler &U = ctx->up;
+        const int h = height / 4, w = width / 4;
+        U.lo_rgb.reserve((size_t)batch * h * w * 3);
+        U.lo_depth.reserve((size_t)batch * h * w);
+        U.hi_rgb.reserve((size_t)batch * width * height * 3);
+        U.hi_depth.reserve((size_t)batch * width * height);
+        U.intr_lo.reserve((size_t)batch * 4);
+        gs_render_opts ro;
+        gs_default_opts(&ro);
+        const float lr0 = opts->lr > 0 ? opts->lr : 1e-3f;
+        const float lr1 = opts->lr_min > 0 ? opts->lr_min : lr0 * 0.05f;
+        for (int s = 0; s < opts->steps; ++s) {
+            int c0 = (int)(((int64_t)s * batch) % n_pairs);
+            if (c0 + batch > n_pairs) c0 = 0;
+            launch_quarter_intr(intrinsics + (int64_t)c0 * 4, batch, U.intr_lo.p, st);
+            int rc = render_impl(ctx, batch, scene_ids + c0, poses + (int64_t)c0 * 12, U.intr_lo.p,
+                                 w, h, U.lo_rgb.p, U.lo_depth.p, nullptr, ro, st, nullptr);
+            if (rc) return rc;
+            rc = render_impl(ctx, batch, scene_ids + c0, poses + (int64_t)c0 * 12,
+                             intrinsics + (int64_t)c0 * 4, width, height, U.hi_rgb.p, U.hi_depth.p,
+                             nullptr, ro, st, nullptr);
+            if (rc) return rc;
+            const float loss = up_loss_and_grads(ctx, batch, h, w, U.lo_rgb.p, U.lo_depth.p,
+                                                 U.hi_rgb.p, U.hi_depth.p, st);
+            const float lr = lr1 + 0.5f * (lr0 - lr1) *
+                                       (1.0f + std::cos(3.14159265f * (float)s /
+                                                        (float)std::max(opts->steps - 1, 1)));
+            up_adam(ctx, lr, st);
+            if (loss_curve) loss_curve[s] = loss;
+        }
+        HIP_CHECK(hipStreamSynchronize(st));
+        return GS_OK;
+    });
+}
+
+int gs_render_batch_upsampled(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids,
+                              const float *poses, const float *intrinsics, int32_t width,
+                              int32_t height, float *rgb, float *depth, float *score_out,
+                              float fallback_threshold, int32_t *n_fallback_out,
+                              const gs_render_opts *opts, void *stream)
+{
+    int rc = validate_render_args(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb,
+                                  depth);
+    if (rc) return rc;
+    if (width % 4 || height % 4)
+        return fail(ctx, GS_ERR_INVALID_ARG, "width and height must be multiples of 4");
+    if (!ctx->up.ready) return fail(ctx, GS_ERR_NOT_TRAINED, "upsampler not initialised");
+    gs_render_opts o;
+    if (opts) o = *opts; else gs_default_opts(&o);
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        hipStream_t st = (hipStream_t)stream;
+        Upsampler &U = ctx->up;
+        const int h = height / 4, w = width / 4;
+        const int64_t lp = (int64_t)h * w, hp = lp * 16;
+        U.lo_rgb.reserve((size_t)n_cams * lp * 3);
+        U.lo_depth.reserve((size_t)n_cams * lp);
+        U.intr_lo.reserve((size_t)n_cams * 4);
+        U.score.reserve((size_t)n_cams);
+        launch_quarter_intr(intrinsics, n_cams, U.intr_lo.p, st);
+        int r = render_impl(ctx, n_cams, scene_ids, poses, U.intr_lo.p, w, h, U.lo_rgb.p,
+                            U.lo_depth.p, nullptr, o, st, nullptr);
+        if (r) return r;
+        const gs_stats lo_stats = ctx->last;
+        if (!U.packed) up_pack(ctx, st);
+        for (int c0 = 0; c0 < n_cams; c0 += kUpChunk) {
+            const int m = std::min(kUpChunk, n_cams - c0);
+            up_alloc(ctx, m, h, w, false);
+            launch_up_input(U.lo_rgb.p + c0 * lp * 3, U.lo_depth.p + c0 * lp, m * lp, U.x0f.p,
+                            U.x0b.p, st);
+            launch_up_score(U.x0f.p, m, h, w, U.score.p + c0, st);
+            up_forward(ctx, m, h, w, st);
+            launch_up_head(false, U.x0f.p, U.y4.p, h, w, m, rgb + c0 * hp * 3, depth + c0 * hp,
+                           nullptr, nullptr, nullptr, nullptr, st);
+        }
+        if (score_out)
+            HIP_CHECK(hipMemcpyAsync(score_out, U.score.p, (size_t)n_cams * 4,
+                                     hipMemcpyDeviceToDevice, st));
+        // fallback: cameras whose score exceeds the threshold, rendered at full resolution
+        std::vector<float> sc(n_cams);
+        HIP_CHECK(hipMemcpyAsync(sc.data(), U.score.p, (size_t)n_cams * 4, hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        std::vector<int32_t> list;
+        for (int i = 0; i < n_cams; ++i)
+            if (!(sc[i] <= fallback_threshold)) list.push_back(i);
+        const int nf = (int)list.size();
+        if (nf > 0) {
+            std::vector<int32_t> sids(nf);
+            for (int k = 0; k < nf; ++k) sids[k] = scene_ids[list[k]];
+            U.fb_list.reserve(nf);
+            U.fb_poses.reserve((size_t)nf * 12);
+            U.fb_intr.reserve((size_t)nf * 4);
+            for (int k0 = 0; k0 < nf; k0 += kUpChunk) {
+                const int m = std::min(kUpChunk, nf - k0);
+                for (int k = 0; k < m; ++k) {
+                    HIP_CHECK(hipMemcpyAsync(U.fb_poses.p + (size_t)k * 12,
+                                             poses + (size_t)list[k0 + k] * 12, 48,
+                                             hipMemcpyDeviceToDevice, st));
+                    HIP_CHECK(hipMemcpyAsync(U.fb_intr.p + (size_t)k * 4,
+                                             intrinsics + (size_t)list[k0 + k] * 4, 16,
+                                             hipMemcpyDeviceToDevice, st));
+                }
+                HIP_CHECK(hipMemcpyAsync(U.fb_list.p, list.data() + k0, (size_t)m * 4,
+                                         hipMemcpyHostToDevice, st));
+                U.fb_rgb.reserve((size_t)m * hp * 3);
+                U.fb_depth.reserve((size_t)m * hp);
+                r = render_impl(ctx, m, sids.data() + k0, U.fb_poses.p, U.fb_intr.p, width, height,
+                                U.fb_rgb.p, U.fb_depth.p, nullptr, o, st, nullptr);
+                if (r) return r;
+                launch_copy_flagged(U.fb_list.p, m, hp, U.fb_rgb.p, U.fb_depth.p, rgb, depth, st);
+            }
+        }
+        HIP_CHECK(hipStreamSynchronize(st));
+        ctx->last = lo_stats;
+        if (n_fallback_out) *n_fallback_out = nf;
+        return GS_OK;
+    });
+}
+
+int gs_frame_psnr(gs_ctx *ctx, int32_t n, int64_t npix, const float *a, const float *b, float *out,
+                  void *stream)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (n < 1 || npix < 1 || !a || !b || !out) return fail(ctx, GS_ERR_INVALID_ARG, "bad PSNR arguments");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        launch_frame_psnr(a, b, n, npix, out, (hipStream_t)stream);
+        HIP_CHECK(hipGetLastError());
         return GS_OK;
     });
 }

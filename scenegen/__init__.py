@@ -277,6 +277,30 @@ def make_cameras(k: int, step: int = 0, subset=None) -> dict:
     return out
 
 
+def sampled_cameras(k: int, count: int, seed: int) -> dict:
+    """`count` independent cameras over the scenes of workload k (training
+    and calibration sets of the learned upsampler): scene uniform, position
+    uniform over the slab minus a 1 m margin, heading uniform, 0.5 m above
+    the heightfield, 15 degrees down. Seeds are offset so they never
+    coincide with the evaluation trajectories."""
+    w = workload(k)
+    rng = np.random.default_rng(7_000_000 + 1000 * seed + k)
+    lim = w.extent - 1.0
+    sids = rng.integers(0, w.n_scenes, size=count).astype(np.int32)
+    pos = rng.uniform(-lim, lim, size=(count, 2))
+    head = rng.uniform(0.0, 2.0 * np.pi, size=count)
+    poses = np.zeros((count, 3, 4), np.float64)
+    hfs = {}
+    for s in np.unique(sids):
+        hfs[int(s)] = heightfield(k, int(s))
+    for i in range(count):
+        zc = float(hfs[int(sids[i])](pos[i, 0], pos[i, 1])) + 0.5
+        poses[i] = look_pose((pos[i, 0], pos[i, 1], zc), head[i], math.radians(15.0))
+    intr = np.tile(np.array([w.fx, w.fy, w.cx, w.cy], np.float32), (count, 1))
+    return dict(scene_ids=sids, poses=poses.astype(np.float32), intrinsics=intr,
+                width=w.width, height=w.height)
+
+
 def camera_subset(k: int, count: int, seed: int = 12345) -> np.ndarray:
     """Seeded subset of camera indices of workload k (sorted)."""
     rng = np.random.default_rng(seed + k)
