@@ -81,6 +81,75 @@ def cpu_baseline(scenes, cams, W, H, budget_s, threads):
                       f"workload, FP64 oracle, {dt:.1f}s"}
 
 
+def learned_form(args, r, sids, scene_ids, P, K, W, H, n, out, ms_graph, torch):
+    """Train the 4x upsampler on rendered pairs, calibrate the fallback
+    threshold on held-out cameras, then time the upsampled render of the
+    evaluation batch and score it against the full-resolution render."""
+    import scenegen
+    k = args.workload
+    # the method without the network: bilinear upsampling (untrained net)
+    cal = scenegen.sampled_cameras(k, args.calib_cams, seed=2)
+    cal_ids = np.array([sids[i] for i in cal["scene_ids"]], np.int32)
+    Pc = torch.as_tensor(cal["poses"]).cuda()
+    Kc = torch.as_tensor(cal["intrinsics"]).cuda()
+    full_c = r.render(cal_ids, Pc, Kc, W, H, alpha=False)
+    r.up_init(0)
+    up_c = r.render_upsampled(cal_ids, Pc, Kc, W, H)
+    psnr_bilinear = r.frame_psnr(up_c[0], full_c[0]).cpu().numpy()
+    # training on seeded pairs disjoint from calibration and evaluation
+    tr = scenegen.sampled_cameras(k, args.train_pairs, seed=1)
+    tr_ids = np.array([sids[i] for i in tr["scene_ids"]], np.int32)
+    steps = max(1, args.train_pairs // args.train_batch)
+    t = time.time()
+    curve = r.up_train(tr_ids, tr["poses"], tr["intrinsics"], W, H, batch=args.train_batch,
+                       steps=steps, lr=2e-3, lr_min=1e-4)
+    t_train = time.time() - t
+    log(f"trained upsampler: {steps} steps x {args.train_batch} pairs in {t_train:.1f}s, "
+        f"loss {curve[:10].mean():.5f} -> {curve[-10:].mean():.5f}")
+    # calibration: largest score below which every held-out frame reaches the target
+    up_c = r.render_upsampled(cal_ids, Pc, Kc, W, H)
+    psnr_c = r.frame_psnr(up_c[0], full_c[0]).cpu().numpy()
+    score_c = up_c[2].cpu().numpy()
+    order = np.argsort(score_c)
+    bad = np.nonzero(psnr_c[order] < args.psnr_target)[0]
+    if len(bad) == 0:
+        thr = float("inf")
+    elif bad[0] == 0:
+        thr = -1.0
+    else:
+        thr = float(score_c[order][bad[0] - 1])
+    log(f"calibration: PSNR trained mean {psnr_c.mean():.2f} dB vs bilinear "
+        f"{psnr_bilinear.mean():.2f} dB; threshold {thr:.4g} accepts "
+        f"{(score_c <= thr).mean():.1%} of held-out frames")
+    del full_c, up_c
+    # timed: the evaluation batch
+    uo = (torch.empty_like(out[0]), torch.empty_like(out[1]), None)
+
+    def step_learned():
+        return r.render_upsampled(scene_ids, P, K, W, H, threshold=thr, out=uo)
+
+    step_learned()
+    ms = time_steps(step_learned, args.steps, torch) * 1e3
+    rgb_u, depth_u, score_u, nf = step_learned()
+    psnr_e = r.frame_psnr(rgb_u, out[0]).cpu().numpy()
+    fin = np.where(np.isfinite(psnr_e), psnr_e, 200.0)
+    log(f"learned: {ms:.2f} ms/step, {n / ms * 1e3:.0f} frames/s, fallback {nf}/{n}, "
+        f"PSNR mean {fin.mean():.2f} p5 {np.percentile(fin, 5):.2f} min {fin.min():.2f}")
+    return {"ms_per_step": ms, "frames_per_s": n / ms * 1e3, "speedup_over_batched": ms_graph / ms,
+            "fallback_rate": nf / n, "fallback_threshold": thr,
+            "psnr_db": {"mean": float(fin.mean()), "p5": float(np.percentile(fin, 5)),
+                        "min": float(fin.min()),
+                        "frac_ge_target": float((fin >= args.psnr_target).mean()),
+                        "target": args.psnr_target,
+                        "reference": "full-res render of the same cameras (fallback frames: "
+                                     "exact, counted as 200 dB)"},
+            "psnr_upsampled_only_db": {"heldout_mean_trained": float(psnr_c.mean()),
+                                       "heldout_mean_bilinear": float(psnr_bilinear.mean())},
+            "train": {"pairs": int(steps * args.train_batch), "batch": args.train_batch,
+                      "steps": steps, "seconds": t_train, "loss_first": float(curve[:10].mean()),
+                      "loss_last": float(curve[-10:].mean())}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +162,11 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="run the autotuner first")
     ap.add_argument("--only-batched", action="store_true",
                     help="time only the graph-replayed batched form (for profiling)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-upsample form")
+    ap.add_argument("--train-pairs", type=int, default=100_000)
+    ap.add_argument("--train-batch", type=int, default=64)
+    ap.add_argument("--calib-cams", type=int, default=512)
+    ap.add_argument("--psnr-target", type=float, default=35.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -188,6 +262,10 @@ def main():
             forms["plain"] = {"ms_per_step": ms_plain, "frames_per_s": n / ms_plain * 1e3}
             log(f"plain: {ms_plain:.1f} ms/step")
             forms["batched"]["speedup_over_plain"] = ms_plain / ms_graph
+
+    if not args.only_batched and not args.no_learned and args.workload == 2:
+        forms["learned"] = learned_form(args, r, sids, scene_ids, P, K, W, H, n, out, ms_graph,
+                                        torch)
 
     cpu = None
     if not args.no_cpu:

@@ -300,8 +300,10 @@ struct Pixel {
 // One step of the walk for one (pixel, Gaussian) pair: alpha clamped to
 // 0.99; skipped below 1/255; the walk stops (without this Gaussian) when the
 // new transmittance would fall under 1e-4; otherwise weight alpha T is
-// accumulated into colour and depth.
-__device__ __forceinline__ void composite(Pixel &s, float px, float py, float4 A, float4 B,
+// accumulated into colour and depth. Branch-free: a pair that does not
+// accumulate adds a zero weight, which leaves every sum bitwise unchanged.
+// Returns whether the pair was accumulated.
+__device__ __forceinline__ bool composite(Pixel &s, float px, float py, float4 A, float4 B,
                                           float4 C)
 {
     const float dx = px - A.x, dy = py - A.y;
@@ -309,19 +311,18 @@ __device__ __forceinline__ void composite(Pixel &s, float px, float py, float4 A
     const float f = B.x * dy;
     const float q = fmaf(e, e, f * f);
     const float alpha = fminf(kAlphaMax, B.y * __builtin_amdgcn_exp2f(-q));
-    if (alpha >= kAlphaMin) {
-        const float Tn = s.T * (1.0f - alpha);
-        if (Tn < kTMin) {
-            s.done = true;
-        } else {
-            const float w = alpha * s.T;
-            s.r = fmaf(w, B.z, s.r);
-            s.g = fmaf(w, B.w, s.g);
-            s.b = fmaf(w, C.x, s.b);
-            s.zw = fmaf(w, C.y, s.zw);
-            s.T = Tn;
-        }
-    }
+    const bool hit = (alpha >= kAlphaMin) & !s.done;
+    const float Tn = s.T * (1.0f - alpha);
+    const bool stop = hit & (Tn < kTMin);
+    const bool acc = hit & !stop;
+    s.done = s.done | stop;
+    const float w = acc ? alpha * s.T : 0.0f;
+    s.r = fmaf(w, B.z, s.r);
+    s.g = fmaf(w, B.w, s.g);
+    s.b = fmaf(w, C.x, s.b);
+    s.zw = fmaf(w, C.y, s.zw);
+    s.T = acc ? Tn : s.T;
+    return acc;
 }
 
 }  // namespace gs

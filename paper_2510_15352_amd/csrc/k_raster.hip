@@ -95,18 +95,37 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
             }
         }
         __syncthreads();  // per-wave lists written before they are read
-        if (!s.done) {
-            for (int k = 0; k < n; ++k) {
+        if (__ballot(!s.done) != 0ull) {
+            // four list entries per step (one 8-byte LDS read), a wave-level
+            // completion test after each step, then the remainder one by one
+            int k = 0;
+            bool live = true;
+            for (; k + 4 <= n; k += 4) {
+                const uint2 jj = *reinterpret_cast<const uint2 *>(list + k);
+                const int j[4] = {(int)(jj.x & 0xffffu), (int)(jj.x >> 16), (int)(jj.y & 0xffffu),
+                                  (int)(jj.y >> 16)};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (COUNT) {
+                        n_eval += !s.done;
+                        n_contrib += composite(s, px, py, sA[j[u]], sB[j[u]], sC[j[u]]);
+                    } else {
+                        composite(s, px, py, sA[j[u]], sB[j[u]], sC[j[u]]);
+                    }
+                }
+                if (__ballot(!s.done) == 0ull) {
+                    live = false;
+                    break;
+                }
+            }
+            for (; live && k < n; ++k) {
                 const int j = list[k];
                 if (COUNT) {
-                    const float Tb = s.T;
-                    composite(s, px, py, sA[j], sB[j], sC[j]);
-                    ++n_eval;
-                    n_contrib += s.T != Tb;
+                    n_eval += !s.done;
+                    n_contrib += composite(s, px, py, sA[j], sB[j], sC[j]);
                 } else {
                     composite(s, px, py, sA[j], sB[j], sC[j]);
                 }
-                if (s.done) break;
             }
         }
         if (__syncthreads_count(!s.done) == 0) break;
@@ -137,7 +156,7 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
 
 #define GS_RASTER_SHARED                      \
     __shared__ float4 sA[B], sB[B], sC[B];    \
-    __shared__ uint16_t sL[(TW * TH / 64) * B];
+    __shared__ __attribute__((aligned(16))) uint16_t sL[(TW * TH / 64) * B];
 
 template <int TW, int TH, int B>
 __global__ __launch_bounds__(TW *TH) void k_raster(RasterArgs a)
