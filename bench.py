@@ -63,11 +63,11 @@ def time_steps(fn, steps, torch):
     return (time.perf_counter() - t0) / steps
 
 
-def cpu_baseline(scenes, cams, W, H, budget_s, threads):
+def cpu_baseline(k, scenes, cams, W, H, budget_s, threads):
     """The FP64 oracle on a seeded sample of the same cameras."""
     import oracle
     import scenegen
-    order = scenegen.camera_subset(2, len(cams["scene_ids"]), seed=777)
+    order = scenegen.camera_subset(k, len(cams["scene_ids"]), seed=777)
     done, t0 = 0, time.perf_counter()
     for c in order:
         sc = scenes[int(cams["scene_ids"][c])]
@@ -153,7 +153,8 @@ def learned_form(args, r, sids, scene_ids, P, K, W, H, n, out, ms_graph, torch):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 5; 100 consecutive sim steps for workload 4)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 4])
     ap.add_argument("--plain-steps", type=int, default=1)
@@ -168,6 +169,8 @@ def main():
     ap.add_argument("--calib-cams", type=int, default=512)
     ap.add_argument("--psnr-target", type=float, default=35.0)
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 100 if args.workload == 4 else 5
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(cameras shard across GPUs with no exchange; see the design notes)",
@@ -199,17 +202,33 @@ def main():
         tuned = r.stats()
         log(f"autotune done in {time.time() - t:.1f}s")
 
-    # batched + graph: the headline form
+    # batched + graph: the headline form. Workload 4 advances every camera
+    # along its trajectory each sim step: the step's poses are copied into
+    # the buffer the captured graph reads, then the graph is replayed (every
+    # stage, sorts included, recomputed).
+    traj = None
+    if w.steps > 1:
+        import scenegen
+        t = time.time()
+        traj = torch.as_tensor(scenegen.camera_steps(args.workload, w.steps)["poses"]).cuda()
+        log(f"{w.steps} steps of trajectories in {time.time() - t:.1f}s")
+    sim_step = [0]
+
     def step_graph():
+        if traj is not None:
+            P.copy_(traj[sim_step[0] % w.steps])
+            sim_step[0] += 1
         r.render(scene_ids, P, K, W, H, out=out, use_graph=True)
 
     for i in range(args.warmup):
         step_graph()
         log(f"warmup step {i} done")
+    sim_step[0] = 0
     ms_graph = time_steps(step_graph, args.steps, torch) * 1e3
     st_graph = r.stats()
     log(f"batched+graph: {ms_graph:.2f} ms/step, {n / ms_graph * 1e3:.0f} frames/s")
-
+    if traj is not None:
+        P.copy_(traj[0])
     forms = {"batched": {"ms_per_step": ms_graph, "frames_per_s": n / ms_graph * 1e3,
                          "choice": {k: st_graph[k] for k in ("tile_w", "tile_h", "lds_batch",
                                                               "chunk_cams", "persistent")}}}
@@ -270,8 +289,21 @@ def main():
     cpu = None
     if not args.no_cpu:
         threads = min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "64")))
-        cpu = cpu_baseline(scenes, cams, W, H, args.cpu_seconds, threads)
+        cpu = cpu_baseline(args.workload, scenes, cams, W, H, args.cpu_seconds, threads)
         log(f"cpu oracle: {cpu['value']:.3f} frames/s on {threads} threads")
+
+    # algorithmic HBM bytes of one step: outputs (RGB + depth [+ alpha], FP32),
+    # every scene's parameters read once, 24 B per tile instance
+    b_g = 44 + 12 * (w.sh_degree + 1) ** 2
+    px_bytes = 12 + 4 + (4 if out[2] is not None else 0)
+    alg_bytes = (float(px_bytes) * W * H * n + float(sum(len(s["opacity"]) for s in scenes)) * b_g
+                 + 24.0 * float(st_graph["instances"]))
+    hbm = {"algorithmic_bytes_per_step": alg_bytes,
+           "GB_per_s": alg_bytes / (ms_graph * 1e-3) / 1e9,
+           "frac_of_peak": alg_bytes / (ms_graph * 1e-3) / HBM_PEAK,
+           "model": f"{px_bytes} B/pixel out + {b_g} B per Gaussian once + 24 B per instance",
+           "instances_per_step": st_graph["instances"], "visible_per_step": st_graph["visible"]}
+    log(f"algorithmic HBM traffic {alg_bytes / 1e9:.2f} GB/step = {hbm['GB_per_s']:.0f} GB/s")
 
     line = {
         "metric": METRIC, "value": n / ms_graph * 1e3, "unit": "frames/s", "n_gpus": 1,
@@ -280,8 +312,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "cams": n, "width": W, "height": H,
                    "scenes": w.n_scenes, "gaussians": int(sum(len(s["opacity"]) for s in scenes)),
-                   "sh_degree": w.sh_degree, "form": "batched, hipGraph replay"},
-        "forms": forms, "roofline": roofline, "cpu_baseline": cpu,
+                   "sh_degree": w.sh_degree, "sim_steps": w.steps,
+                   "form": "batched, hipGraph replay" + (
+                       ", poses advanced every sim step" if w.steps > 1 else "")},
+        "forms": forms, "roofline": roofline, "cpu_baseline": cpu, "hbm_algorithmic": hbm,
     }
     if tuned:
         line["config"]["autotuned"] = {k: tuned[k] for k in ("tile_w", "tile_h", "lds_batch",

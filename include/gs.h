@@ -80,7 +80,7 @@ typedef struct {
     int32_t tile_w;    /* raster tile width in pixels; 0 = tuned/default (16) */
     int32_t tile_h;    /* raster tile height; 0 = tuned/default (16) */
     int32_t lds_batch; /* Gaussians staged in LDS per batch; 0 = tuned/default (256) */
-    int32_t chunk_cams;/* BATCHED: cameras per chunk; 0 = tuned/default */
+    int32_t chunk_cams;/* BATCHED: cameras per chunk (1..4096); 0 = tuned/default */
     int32_t persistent;/* BATCHED: raster as a persistent work queue (1), a grid (0), -1 = tuned */
     int32_t use_graph; /* BATCHED: capture the step into a HIP graph and replay it (1) */
     int32_t timing;    /* record HIP events around every stage (eager renders only) */
@@ -164,11 +164,48 @@ int gs_render_batch(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const
                     const float *intrinsics, int32_t width, int32_t height, float *rgb,
                     float *depth, float *alpha, const gs_render_opts *opts, void *stream);
 
+/* Camera-rate decimation (the paper renders at the camera's own frame rate,
+ * below the control rate, Sec. 3.3; staggering the environments over the
+ * period, so that every step renders a similar share, is this library's
+ * choice):
+ * renders only the cameras due at sim_step, camera i being due when
+ * (sim_step + phase[i]) mod period == 0, into their own output slots; the
+ * other cameras' slots are left untouched (they keep their last frame).
+ * phase: HOST int32 [n_cams] (values >= 0), or NULL for phase[i] = i, which
+ * spreads the cameras evenly over the period. Other arguments as
+ * gs_render_batch (the batch is the full camera set; the per-subset plan and
+ * graph are cached per distinct subset). *n_due_out (HOST, nullable)
+ * receives the number of cameras rendered; with none due nothing is
+ * enqueued. Asynchronous on stream. */
+int gs_render_due(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const float *poses,
+                  const float *intrinsics, int32_t width, int32_t height, int64_t sim_step,
+                  int32_t period, const int32_t *phase, float *rgb, float *depth, float *alpha,
+                  const gs_render_opts *opts, int32_t *n_due_out, void *stream);
+
+/* Motion blur (Sec. 3.3 and the appendix figure on motion blur: frames
+ * offset along the camera's velocity over the shutter interval, blended into
+ * one image). Sub-frame k < n_sub renders camera i from centre
+ * C_i - v_i * dt_k, dt_k = shutter * (k + 1/2) / n_sub (the middle of the
+ * k-th equal part of the exposure [t - shutter, t]; rotation unchanged).
+ * Output: rgb and alpha are the means over the sub-frames, depth the
+ * alpha-weighted mean of the sub-frame depths (0 where all are empty).
+ *   velocities DEVICE f32 [n_cams][3], world frame (m/s); shutter >= 0 (s);
+ *   1 <= n_sub <= 16; other arguments as gs_render_batch (alpha nullable;
+ *   the library then keeps the weight sums in its own buffer).
+ * Asynchronous on stream; sub-frames run as n_sub batched renders that add
+ * into the outputs (captured graphs per sub-frame when use_graph is set). */
+int gs_render_batch_motion_blur(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids,
+                                const float *poses, const float *velocities,
+                                const float *intrinsics, int32_t width, int32_t height,
+                                float shutter, int32_t n_sub, float *rgb, float *depth,
+                                float *alpha, const gs_render_opts *opts, void *stream);
+
 /* Counters and choices of the last gs_render_batch of the context. */
 int gs_last_stats(gs_ctx *ctx, gs_stats *out);
 
-/* Set the instance-buffer capacity (entries) used by the next render; the
- * library still grows it on overflow. Drops captured graphs. cap >= 1. */
+/* Set the instance-buffer capacity (entries per chunk) used by the next
+ * render; the library still grows it on overflow, up to 2^31. Drops captured
+ * graphs. 1 <= cap <= 2^31, else GS_ERR_INVALID_ARG. */
 int gs_set_instance_capacity(gs_ctx *ctx, int64_t cap);
 
 /* Destroy every captured graph of the context (releases their scene refs). */
@@ -227,6 +264,15 @@ int gs_upsampler_init(gs_ctx *ctx, uint64_t seed);
 /* Copy the parameter vector in (host, n values) or out. Setting resets Adam. */
 int gs_upsampler_set_weights(gs_ctx *ctx, const float *params, int64_t n);
 int gs_upsampler_get_weights(gs_ctx *ctx, float *params, int64_t n);
+
+/* Checkpoint: parameter vector, Adam moments and Adam step to / from a file
+ * (little-endian: "GSUPCKPT", u32 version 1, u32 0, i64 parameter count,
+ * i32 step, u32 0, then 3 x count FP32: parameters, first moments, second
+ * moments, each in the parameter-vector layout). Load restores the training
+ * state exactly; a file of another version or size is GS_ERR_INVALID_ARG.
+ * Synchronous. */
+int gs_upsampler_save(gs_ctx *ctx, const char *path);
+int gs_upsampler_load(gs_ctx *ctx, const char *path);
 
 /* Network forward on given low-res frames.
  *   rgb_lo [n][h][w][3], depth_lo [n][h][w] DEVICE; outputs rgb_out

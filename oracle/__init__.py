@@ -171,6 +171,41 @@ def render(scene: dict, pose, intr, width: int, height: int, near: float = 0.2,
                   vp[:k][order], vv[:k][order])
 
 
+def blur_subposes(pose, velocity, shutter: float, n_sub: int) -> np.ndarray:
+    """Camera poses of the sub-frames of a motion-blurred frame (Sec. 3.3 and
+    the appendix figure on motion blur: frames offset along the camera's
+    velocity, blended into one image). Reading: sub-frame k is the camera at
+    the middle of the k-th of n_sub equal parts of the exposure [t - shutter,
+    t], centre C - v (shutter (k + 1/2) / n_sub), rotation unchanged. The
+    sub-frame poses are renderer inputs, so they are formed in FP32 (one
+    rounded product and one rounded difference per coordinate)."""
+    pose = _f32(pose).reshape(3, 4)
+    v = _f32(velocity).reshape(3)
+    out = np.repeat(pose[None], n_sub, axis=0)
+    sh = float(np.float32(shutter))
+    for k in range(n_sub):
+        dt = np.float32(sh * (k + 0.5) / n_sub)
+        out[k, :, 3] = pose[:, 3] - v * dt
+    return out
+
+
+def render_motion_blur(scene: dict, pose, velocity, intr, width: int, height: int,
+                       shutter: float, n_sub: int, near: float = 0.2, bg=(0.0, 0.0, 0.0),
+                       threads: int = 0):
+    """Motion-blurred frame: the n_sub sub-frames rendered by `render` and
+    blended with equal weights. Reading of the blend: RGB and accumulated
+    weight are the means over the sub-frames; depth stays an expected depth,
+    sum_k alpha_k depth_k / sum_k alpha_k (0 where every sub-frame is
+    empty). Returns (rgb, depth, alpha, [per-sub-frame Render])."""
+    subs = [render(scene, p, intr, width, height, near=near, bg=bg, threads=threads)
+            for p in blur_subposes(pose, velocity, shutter, n_sub)]
+    rgb = sum(r.rgb for r in subs) / n_sub
+    asum = sum(r.alpha for r in subs)
+    zsum = sum(r.alpha * r.depth for r in subs)
+    depth = np.where(asum > 0, zsum / np.where(asum > 0, asum, 1.0), 0.0)
+    return rgb, depth, asum / n_sub, subs
+
+
 def pixel_trace(scene: dict, pose, intr, width: int, height: int, i: int, j: int,
                 near: float = 0.2, eps_alpha: float = DEFAULT_MARGINS[0], cap: int = 256):
     """Candidates of pixel (i, j) in walk order: rows (g, z, alpha, T before,

@@ -23,10 +23,13 @@ GS_MODE_PLAIN, GS_MODE_BATCHED = 0, 1
 
 # every symbol include/gs.h declares
 EXPORTS = ("gs_abi_sizes", "gs_default_opts", "gs_create", "gs_destroy", "gs_last_error", "gs_upload_scene",
-           "gs_release_scene", "gs_scene_size", "gs_render_batch", "gs_last_stats",
+           "gs_release_scene", "gs_scene_size", "gs_render_batch", "gs_render_due",
+           "gs_render_batch_motion_blur",
+           "gs_last_stats",
            "gs_debug_project", "gs_autotune", "gs_set_instance_capacity", "gs_clear_graphs",
            "gs_upsampler_num_params", "gs_upsampler_init", "gs_upsampler_set_weights",
-           "gs_upsampler_get_weights", "gs_upsampler_forward", "gs_upsampler_grads",
+           "gs_upsampler_get_weights", "gs_upsampler_save", "gs_upsampler_load",
+           "gs_upsampler_forward", "gs_upsampler_grads",
            "gs_upsampler_train", "gs_render_batch_upsampled", "gs_frame_psnr")
 
 
@@ -93,6 +96,10 @@ def load():
     L.gs_scene_size.restype = i64
     L.gs_render_batch.argtypes = [vp, i32, vp, vp, vp, i32, i32, vp, vp, vp,
                                   ctypes.POINTER(RenderOpts), vp]
+    L.gs_render_due.argtypes = [vp, i32, vp, vp, vp, i32, i32, i64, i32, vp, vp, vp, vp,
+                                ctypes.POINTER(RenderOpts), ctypes.POINTER(i32), vp]
+    L.gs_render_batch_motion_blur.argtypes = [vp, i32, vp, vp, vp, vp, i32, i32, fp, i32, vp, vp,
+                                              vp, ctypes.POINTER(RenderOpts), vp]
     L.gs_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.gs_debug_project.argtypes = [vp, i32, vp, vp, i32, i32, fp, vp]
     L.gs_autotune.argtypes = [vp, i32, vp, vp, vp, i32, i32, vp, vp, ctypes.c_char_p, vp]
@@ -103,6 +110,8 @@ def load():
     L.gs_upsampler_init.argtypes = [vp, ctypes.c_uint64]
     L.gs_upsampler_set_weights.argtypes = [vp, vp, i64]
     L.gs_upsampler_get_weights.argtypes = [vp, vp, i64]
+    L.gs_upsampler_save.argtypes = [vp, ctypes.c_char_p]
+    L.gs_upsampler_load.argtypes = [vp, ctypes.c_char_p]
     L.gs_upsampler_forward.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
     L.gs_upsampler_grads.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp]
     L.gs_upsampler_train.argtypes = [vp, ctypes.POINTER(TrainOpts), i32, vp, vp, vp, i32, i32, vp,
@@ -244,6 +253,57 @@ class Renderer:
             ctypes.byref(o), _stream_ptr(torch)))
         return rgb, depth, al
 
+    def render_motion_blur(self, scene_ids, poses, velocities, intrinsics, width, height,
+                           shutter, n_sub, out=None, alpha=True, opts=None, **kw):
+        """Motion-blurred render: n_sub sub-frames along each camera's
+        velocity over the shutter interval, blended; returns (rgb, depth,
+        alpha) device tensors."""
+        torch = self.torch
+        sids = np.ascontiguousarray(np.asarray(scene_ids, dtype=np.int32).reshape(-1))
+        n = len(sids)
+        P = _dev_f32(torch, poses, self.device)
+        V = _dev_f32(torch, velocities, self.device)
+        K = _dev_f32(torch, intrinsics, self.device)
+        if P.numel() != n * 12 or K.numel() != n * 4 or V.numel() != n * 3:
+            raise ValueError("poses [n,3,4], velocities [n,3] and intrinsics [n,4] expected")
+        rgb, depth, al = out if out is not None else self.alloc_outputs(n, width, height, alpha)
+        o = opts if opts is not None else self.opts(**kw)
+        self._check(self.lib.gs_render_batch_motion_blur(
+            self.ctx, n, sids.ctypes.data, P.data_ptr(), V.data_ptr(), K.data_ptr(), int(width),
+            int(height), float(shutter), int(n_sub), rgb.data_ptr(), depth.data_ptr(),
+            al.data_ptr() if al is not None else None, ctypes.byref(o), _stream_ptr(torch)))
+        return rgb, depth, al
+
+    def render_due(self, scene_ids, poses, intrinsics, width, height, sim_step, period,
+                   out, phase=None, opts=None, **kw):
+        """Camera-rate decimation: render only the cameras due at `sim_step`
+        into `out` (rgb, depth, alpha), leaving the other slots untouched;
+        returns the number of cameras rendered."""
+        torch = self.torch
+        sids = np.ascontiguousarray(np.asarray(scene_ids, dtype=np.int32).reshape(-1))
+        n = len(sids)
+        P = poses if (torch.is_tensor(poses) and poses.is_cuda and poses.dtype == torch.float32
+                      and poses.is_contiguous()) else _dev_f32(torch, poses, self.device)
+        K = intrinsics if (torch.is_tensor(intrinsics) and intrinsics.is_cuda
+                           and intrinsics.dtype == torch.float32 and intrinsics.is_contiguous()) \
+            else _dev_f32(torch, intrinsics, self.device)
+        if P.numel() != n * 12 or K.numel() != n * 4:
+            raise ValueError("poses must be [n,3,4] and intrinsics [n,4]")
+        ph = None
+        if phase is not None:
+            ph = np.ascontiguousarray(np.asarray(phase, dtype=np.int32).reshape(-1))
+            if len(ph) != n:
+                raise ValueError("phase must hold one value per camera")
+        rgb, depth, al = out
+        o = opts if opts is not None else self.opts(**kw)
+        nd = ctypes.c_int32(0)
+        self._check(self.lib.gs_render_due(
+            self.ctx, n, sids.ctypes.data, P.data_ptr(), K.data_ptr(), int(width), int(height),
+            int(sim_step), int(period), ph.ctypes.data if ph is not None else None,
+            rgb.data_ptr(), depth.data_ptr(), al.data_ptr() if al is not None else None,
+            ctypes.byref(o), ctypes.byref(nd), _stream_ptr(torch)))
+        return nd.value
+
     def stats(self) -> dict:
         s = Stats()
         self._check(self.lib.gs_last_stats(self.ctx, ctypes.byref(s)))
@@ -286,6 +346,12 @@ class Renderer:
         p = np.zeros(self.up_num_params(), np.float32)
         self._check(self.lib.gs_upsampler_get_weights(self.ctx, p.ctypes.data, len(p)))
         return p
+
+    def up_save(self, path):
+        self._check(self.lib.gs_upsampler_save(self.ctx, os.fsencode(path)))
+
+    def up_load(self, path):
+        self._check(self.lib.gs_upsampler_load(self.ctx, os.fsencode(path)))
 
     def up_forward(self, rgb_lo, depth_lo):
         torch = self.torch

@@ -191,14 +191,15 @@ __device__ __forceinline__ TileBox tile_box(uint2 r, int tw, int th)
     return b;
 }
 
-// Can the Gaussian (A, f_y, tau) reach alpha >= 1/255 at some pixel centre
-// of the pixel rectangle [px0, px1] x [py0, py1] (inclusive indices)?
-__device__ __forceinline__ bool may_touch(float4 A, float fy, float tau, int px0, int px1, int py0,
-                                          int py1)
+// Can the Gaussian (conic factor ex, ey, fy; threshold tau) reach alpha >=
+// 1/255 at some pixel centre of a rectangle? Tile-local form: the pixels are
+// lx in [x0, x1], ly in [y0, y1] (integers, tile-local), offsets (Xo, Yo) =
+// tile origin + 0.5 - (u, v), as in the LDS form of the compositing step.
+__device__ __forceinline__ bool may_touch_local(float ex, float ey, float fy, float Xo, float Yo,
+                                                float tau, int x0, int x1, int y0, int y1)
 {
-    const float X0 = (float)px0 + 0.5f - A.x, X1 = (float)px1 + 0.5f - A.x;
-    const float Y0 = (float)py0 + 0.5f - A.y, Y1 = (float)py1 + 0.5f - A.y;
-    return rect_min_q(A.z, A.w, fy, X0, X1, Y0, Y1) <= tau;
+    return rect_min_q(ex, ey, fy, (float)x0 + Xo, (float)x1 + Xo, (float)y0 + Yo,
+                      (float)y1 + Yo) <= tau;
 }
 
 // EWA projection of one Gaussian into one camera (steps: cull at the near
@@ -291,37 +292,43 @@ __device__ __forceinline__ bool project_gaussian(const CamParams &cam, float4 po
     return true;
 }
 
-// Per-pixel state of the front-to-back walk.
+// Per-pixel state of the front-to-back walk. The sign of T carries the stop
+// flag: T > 0 while the pixel is live; a stop negates it, keeping |T| as the
+// final transmittance.
 struct Pixel {
     float T, r, g, b, zw;
-    bool done;
 };
 
+// LDS form of a record for one tile, with (lx, ly) the pixel's position in
+// the tile (integers) and (Xo, Yo) = tile origin + 0.5 - (u, v):
+//   A = (ex, ey, E0, fy), B = (F0, -log2(opacity), r, g), C = (b, z),
+//   E0 = ex Xo + ey Yo, F0 = fy Yo,
+// so that the conic factor terms are e = ex lx + ey ly + E0, f = fy ly + F0
+// and opacity * exp2(-(e^2 + f^2)) = exp2(-(e^2 + f^2 - log2(opacity))).
+//
 // One step of the walk for one (pixel, Gaussian) pair: alpha clamped to
 // 0.99; skipped below 1/255; the walk stops (without this Gaussian) when the
 // new transmittance would fall under 1e-4; otherwise weight alpha T is
 // accumulated into colour and depth. Branch-free: a pair that does not
-// accumulate adds a zero weight, which leaves every sum bitwise unchanged.
+// accumulate adds a zero weight, which leaves every sum bitwise unchanged;
+// once stopped, T < 0 makes every later Tn negative, so nothing accumulates.
 // Returns whether the pair was accumulated.
-__device__ __forceinline__ bool composite(Pixel &s, float px, float py, float4 A, float4 B,
-                                          float4 C)
+__device__ __forceinline__ bool composite(Pixel &s, float lx, float ly, float4 A, float4 B,
+                                          float2 C)
 {
-    const float dx = px - A.x, dy = py - A.y;
-    const float e = fmaf(A.w, dy, A.z * dx);
-    const float f = B.x * dy;
-    const float q = fmaf(e, e, f * f);
-    const float alpha = fminf(kAlphaMax, B.y * __builtin_amdgcn_exp2f(-q));
-    const bool hit = (alpha >= kAlphaMin) & !s.done;
+    const float e = fmaf(A.x, lx, fmaf(A.y, ly, A.z));
+    const float f = fmaf(A.w, ly, B.x);
+    const float q = fmaf(e, e, fmaf(f, f, B.y));
+    const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(-q));
+    const bool hit = alpha >= kAlphaMin;
     const float Tn = s.T * (1.0f - alpha);
-    const bool stop = hit & (Tn < kTMin);
-    const bool acc = hit & !stop;
-    s.done = s.done | stop;
+    const bool acc = hit & (Tn >= kTMin);
     const float w = acc ? alpha * s.T : 0.0f;
     s.r = fmaf(w, B.z, s.r);
     s.g = fmaf(w, B.w, s.g);
     s.b = fmaf(w, C.x, s.b);
     s.zw = fmaf(w, C.y, s.zw);
-    s.T = acc ? Tn : s.T;
+    s.T = acc ? Tn : (hit ? -fabsf(s.T) : s.T);
     return acc;
 }
 

@@ -1,14 +1,16 @@
-// Device-wide scans and a stable LSD radix sort, with element counts read
-// from device memory so that a captured graph needs no host read-back.
+// Device-wide scans and a stable LSD radix sort segmented by camera, with
+// element counts read from device memory so that a captured graph needs no
+// host read-back.
 //
-// All of them use a fixed number of blocks `nb`, each owning one contiguous
+// The scans use a fixed number of blocks `nb`, each owning one contiguous
 // range of ceil(n / nb) elements (reduce-then-scan), so the output order is
 // determined by the input alone, never by scheduling.
 //
 // Two scans end in fused writers instead of an offsets array:
 //   * compaction: exclusive scan of the popcounts of the visibility words,
 //     then each wave writes the set bits of its 64 words, one word at a time,
-//     to consecutive positions (coalesced), as (camera, depth) keys;
+//     to consecutive positions (coalesced), as depth keys, camera-major, and
+//     records where each camera's segment starts;
 //   * instance emission: exclusive scan of the tile counts of the
 //     depth-sorted records, then each wave expands its 64 records into
 //     their tile instances with one lane per output position (load-balanced,
@@ -64,13 +66,6 @@ __device__ __forceinline__ void block_range(uint32_t n, int nb, uint32_t &start,
 __device__ __forceinline__ uint32_t count_of(const uint32_t *n_dev, uint32_t n_host)
 {
     return n_dev ? *n_dev : n_host;
-}
-
-__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
-{
-    const uint32_t lo = __shfl((uint32_t)v, src, 64);
-    const uint32_t hi = __shfl((uint32_t)(v >> 32), src, 64);
-    return ((uint64_t)hi << 32) | lo;
 }
 
 // ----------------------------------------------------------------- loaders --
@@ -189,7 +184,8 @@ void scan_u32(const uint32_t *in, const uint32_t *n_dev, uint32_t n_max, uint32_
 __global__ __launch_bounds__(kBS) void k_compact_down(
     const uint64_t *__restrict__ vis, uint32_t n_words, int nb,
     const uint32_t *__restrict__ partial, const uint32_t *__restrict__ cam_slot, int n_cams,
-    const uint32_t *__restrict__ zbits, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals)
+    const uint32_t *__restrict__ zbits, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+    uint32_t *__restrict__ seg_start)
 {
     __shared__ uint32_t s_wave[kWaves];
     uint32_t start, end;
@@ -215,6 +211,7 @@ __global__ __launch_bounds__(kBS) void k_compact_down(
                 }
                 cam = lo;
             }
+            uint32_t first = cam_slot[cam];
             uint32_t next = cam + 1 < n_cams ? cam_slot[cam + 1] : 0xFFFFFFFFu;
             const uint32_t wlo = (uint32_t)word, whi = (uint32_t)(word >> 32);
             // 8 words per round: their depth bits are loaded together
@@ -230,16 +227,20 @@ __global__ __launch_bounds__(kBS) void k_compact_down(
                 }
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    if (wd[q] == 0ull) continue;
                     const uint32_t wi = w0 + (uint32_t)(w8 + q);
+                    if (wi >= end) break;
                     while ((wi << 6) >= next) {
                         ++cam;
+                        first = next;
                         next = cam + 1 < n_cams ? cam_slot[cam + 1] : 0xFFFFFFFFu;
                     }
                     const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)ex, w8 + q);
+                    // the camera's first word: its segment starts here
+                    if ((wi << 6) == first && lane == 0) seg_start[cam] = base + off;
+                    if (wd[q] == 0ull) continue;
                     if ((wd[q] >> lane) & 1ull) {
                         const uint32_t pos = base + off + (uint32_t)__popcll(wd[q] & lt);
-                        keys[pos] = ((uint64_t)cam << 31) | (uint64_t)zb[q];
+                        keys[pos] = zb[q];
                         vals[pos] = (wi << 6) | lane;
                     }
                 }
@@ -249,22 +250,30 @@ __global__ __launch_bounds__(kBS) void k_compact_down(
     }
 }
 
+// seg_start[n] = total (the end of the last segment).
+__global__ void k_copy_u32(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst)
+{
+    *dst = *src;
+}
+
 void compact_visible(const uint64_t *vis, uint32_t n_words, const uint32_t *cam_slot, int n_cams,
-                     const uint32_t *zbits, uint64_t *keys, uint32_t *vals, uint32_t *n_vis_out,
-                     const ScanTemp &tmp, hipStream_t st)
+                     const uint32_t *zbits, uint32_t *keys, uint32_t *vals, uint32_t *n_vis_out,
+                     uint32_t *seg_start, const ScanTemp &tmp, hipStream_t st)
 {
     if (n_words == 0) return;
     const int nb = scan_reduce(LoadPopc{vis}, nullptr, n_words, n_vis_out, tmp, st);
     hipLaunchKernelGGL(k_compact_down, dim3(nb), dim3(kBS), 0, st, vis, n_words, nb, tmp.partial,
-                       cam_slot, n_cams, zbits, keys, vals);
+                       cam_slot, n_cams, zbits, keys, vals, seg_start);
+    hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, st, n_vis_out, seg_start + n_cams);
 }
+
 // --------------------------------------------------------- fused emission --
 
 __global__ __launch_bounds__(kBS) void k_emit_down(
-    const uint64_t *__restrict__ dkeys, const uint32_t *__restrict__ dvals,
-    const uint32_t *__restrict__ n_dev, int nb, const uint32_t *__restrict__ partial,
-    const uint2 *__restrict__ rect, int tw, int th, int tiles_x, int tiles_per_cam, uint32_t cap,
-    uint32_t *__restrict__ ikeys, uint32_t *__restrict__ ivals)
+    const uint32_t *__restrict__ dvals, const uint32_t *__restrict__ n_dev, int nb,
+    const uint32_t *__restrict__ partial, const uint2 *__restrict__ rect, int tw, int th,
+    int tiles_x, uint32_t cap, uint32_t *__restrict__ ikeys, uint32_t *__restrict__ ivals,
+    uint32_t *__restrict__ ioff)
 {
     __shared__ uint32_t s_wave[kWaves];
     uint32_t start, end;
@@ -278,12 +287,12 @@ __global__ __launch_bounds__(kBS) void k_emit_down(
         if (i < end) {
             slot = dvals[i];
             tb = tile_box(rect[slot], tw, th);
-            kbase = (uint32_t)(dkeys[i] >> 31) * (uint32_t)tiles_per_cam +
-                    (uint32_t)tb.ty0 * (uint32_t)tiles_x + (uint32_t)tb.tx0;
+            kbase = (uint32_t)tb.ty0 * (uint32_t)tiles_x + (uint32_t)tb.tx0;
             cnt = (uint32_t)(tb.bw * tb.bh);
         }
         uint32_t tot;
         const uint32_t ex = block_excl_scan<kWaves>(cnt, tot, s_wave);
+        if (i < end) ioff[i] = base + ex;
         const uint32_t first = __shfl(ex, 0, 64);
         const uint32_t wave_total = __shfl(ex, 63, 64) + __shfl(cnt, 63, 64) - first;
         const uint32_t lex = ex - first;
@@ -310,201 +319,510 @@ __global__ __launch_bounds__(kBS) void k_emit_down(
     }
 }
 
-void emit_instances(const uint64_t *dkeys, const uint32_t *dvals, const uint32_t *n_vis,
-                    uint32_t n_max, const uint2 *rect, int tw, int th, int tiles_x,
-                    int tiles_per_cam, uint32_t cap, uint32_t *ikeys, uint32_t *ivals,
-                    uint32_t *counts, RenderFlags *flags, const ScanTemp &tmp, hipStream_t st)
+// Instance segment of camera c starts at the instance offset of its first
+// record (an empty camera takes the next record's offset, i.e. an empty
+// segment); the last boundary is the number of kept instances.
+__global__ void k_inst_starts(const uint32_t *__restrict__ vis_start, int n_cams,
+                              const uint32_t *__restrict__ ioff,
+                              const uint32_t *__restrict__ counts, uint32_t *__restrict__ inst_start)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > n_cams) return;
+    const uint32_t n_vis = counts[0], kept = counts[2];
+    uint32_t v = kept;
+    if (c < n_cams && vis_start[c] < n_vis) v = min(ioff[vis_start[c]], kept);
+    inst_start[c] = v;
+}
+
+void emit_instances(const uint32_t *dvals, const uint32_t *n_vis, uint32_t n_max,
+                    const uint32_t *vis_start, int n_cams, const uint2 *rect, int tw, int th,
+                    int tiles_x, uint32_t cap, uint32_t *ikeys, uint32_t *ivals, uint32_t *ioff,
+                    uint32_t *inst_start, uint32_t *counts, RenderFlags *flags,
+                    const ScanTemp &tmp, hipStream_t st)
 {
     const int nb = scan_reduce(LoadTiles{dvals, rect, tw, th}, n_vis, n_max, counts + 1, tmp, st);
     launch_finalize_counts(counts, cap, flags, st);
-    hipLaunchKernelGGL(k_emit_down, dim3(nb), dim3(kBS), 0, st, dkeys, dvals, n_vis, nb,
-                       tmp.partial, rect, tw, th, tiles_x, tiles_per_cam, cap, ikeys, ivals);
+    hipLaunchKernelGGL(k_emit_down, dim3(nb), dim3(kBS), 0, st, dvals, n_vis, nb, tmp.partial,
+                       rect, tw, th, tiles_x, cap, ikeys, ivals, ioff);
+    hipLaunchKernelGGL(k_inst_starts, dim3((n_cams + 1 + 255) / 256), dim3(256), 0, st, vis_start,
+                       n_cams, ioff, counts, inst_start);
 }
 
-// ------------------------------------------------------------- radix sort --
+// ------------------------------------------------------ segmented radix sort --
+// Stable LSD sort of (key, value) pairs inside segments [seg[c], seg[c+1]).
+// Each segment is cut into tiles of kSegTile keys; block b handles tile
+// b - tp[c] of segment c (tp = exclusive scan of tiles per segment). The
+// digit histograms are laid out [segment][digit][tile of segment], so one
+// plain exclusive scan over them yields every (segment, digit, tile)'s output
+// position, stable inside the segment.
+constexpr int kSegKPT = 8;
+constexpr int kSegTile = kBS * kSegKPT;
 
-template <typename K, int RB>
-__global__ __launch_bounds__(kBS) void k_radix_hist(const K *__restrict__ keys,
-                                                    const uint32_t *n_dev, int shift, int nb,
-                                                    uint32_t *__restrict__ hist)
+// tp[c] for c <= n_seg (n_seg <= 4096) and hist_len = tp[n_seg] * R.
+__global__ __launch_bounds__(1024) void k_seg_tiles(const uint32_t *__restrict__ seg, int n_seg,
+                                                    int R, uint32_t *__restrict__ tp,
+                                                    uint32_t *__restrict__ hist_len)
 {
-    constexpr int R = 1 << RB;
-    __shared__ uint32_t h[R];
-    for (int d = threadIdx.x; d < R; d += kBS) h[d] = 0;
-    __syncthreads();
-    uint32_t start, end;
-    block_range(*n_dev, nb, start, end);
-    for (uint32_t i = start + threadIdx.x; i < end; i += kBS)
-        atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (uint32_t)(R - 1)], 1u);
-    __syncthreads();
-    for (int d = threadIdx.x; d < R; d += kBS) hist[d * nb + blockIdx.x] = h[d];
-}
-
-// Stable scatter of one RB-bit digit pass. A block walks its range in tiles
-// of 256 * KPT keys. Keys of a tile are ranked sub-tile by sub-tile (256 keys
-// in index order): the rank among equal digits is the count in earlier
-// sub-tiles and waves plus the count of lower lanes of the same wave (peer
-// mask from RB ballots). The tile is then reordered by digit in LDS and
-// written out in that order, so each digit's run goes to consecutive
-// addresses.
-template <typename K, int RB, int KPT>
-__global__ __launch_bounds__(kBS) void k_radix_scatter(
-    const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__restrict__ kout,
-    uint32_t *__restrict__ vout, const uint32_t *n_dev, int shift, int nb,
-    const uint32_t *__restrict__ hist_scanned)
-{
-    constexpr int R = 1 << RB;
-    constexpr int DPT = R / kBS;  // digits owned by each thread
-    constexpr int TILE = kBS * KPT;
-    __shared__ K s_keys[TILE];
-    __shared__ uint32_t s_vals[TILE];
-    __shared__ uint32_t s_cnt[kWaves][R];
-    __shared__ uint32_t s_run[R], s_toff[R], s_base[R];
-    __shared__ uint32_t s_wave[kWaves];
-    const uint32_t tid = threadIdx.x;
-    const int wave = tid >> 6;
-    const uint64_t lt = lanemask_lt();
-    const uint32_t mask = (uint32_t)(R - 1);
+    __shared__ uint32_t s_wave[16];
+    uint32_t v[4], sum = 0;
 #pragma unroll
-    for (int q = 0; q < DPT; ++q) s_base[tid * DPT + q] = hist_scanned[(tid * DPT + q) * nb + blockIdx.x];
-    uint32_t start, end;
-    block_range(*n_dev, nb, start, end);
-    for (uint32_t t0 = start; t0 < end; t0 += TILE) {
-        K key[KPT];
-        uint32_t val[KPT], dig[KPT], lrank[KPT];
+    for (int q = 0; q < 4; ++q) {
+        const int c = (int)threadIdx.x * 4 + q;
+        v[q] = c < n_seg ? (seg[c + 1] - seg[c] + kSegTile - 1) / kSegTile : 0u;
+        sum += v[q];
+    }
+    uint32_t total;
+    uint32_t ex = block_excl_scan<16>(sum, total, s_wave);
 #pragma unroll
-        for (int k = 0; k < KPT; ++k) {
-            const uint32_t i = t0 + k * kBS + tid;
-            key[k] = 0;
-            val[k] = 0;
-            if (i < end) {
-                key[k] = kin[i];
-                val[k] = vin[i];
-            }
-            dig[k] = (uint32_t)(key[k] >> shift) & mask;
-        }
-#pragma unroll
-        for (int q = 0; q < DPT; ++q) s_run[tid * DPT + q] = 0;
-#pragma unroll
-        for (int k = 0; k < KPT; ++k) {
-            const bool valid = t0 + k * kBS + tid < end;
-#pragma unroll
-            for (int q = 0; q < DPT; ++q)
-#pragma unroll
-                for (int w = 0; w < kWaves; ++w) s_cnt[w][tid * DPT + q] = 0;
-            __syncthreads();
-            uint64_t peers = __ballot(valid);
-#pragma unroll
-            for (int bit = 0; bit < RB; ++bit) {
-                const bool on = (dig[k] >> bit) & 1u;
-                const uint64_t m = __ballot(on);
-                peers &= on ? m : ~m;
-            }
-            const uint32_t rank = (uint32_t)__popcll(peers & lt);
-            if (valid && rank == 0) s_cnt[wave][dig[k]] = (uint32_t)__popcll(peers);
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < DPT; ++q) {
-                const int d = tid * DPT + q;
-                uint32_t run = s_run[d];
-#pragma unroll
-                for (int w = 0; w < kWaves; ++w) {
-                    const uint32_t c = s_cnt[w][d];
-                    s_cnt[w][d] = run;
-                    run += c;
-                }
-                s_run[d] = run;
-            }
-            __syncthreads();
-            lrank[k] = valid ? s_cnt[wave][dig[k]] + rank : 0u;
-            __syncthreads();
-        }
-        // tile digit offsets: exclusive scan of the tile's digit counts
-        {
-            uint32_t local[DPT], sum = 0;
-#pragma unroll
-            for (int q = 0; q < DPT; ++q) {
-                local[q] = sum;
-                sum += s_run[tid * DPT + q];
-            }
-            uint32_t tot;
-            const uint32_t ex = block_excl_scan<kWaves>(sum, tot, s_wave);
-#pragma unroll
-            for (int q = 0; q < DPT; ++q) s_toff[tid * DPT + q] = ex + local[q];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < KPT; ++k)
-            if (t0 + k * kBS + tid < end) {
-                const uint32_t p = s_toff[dig[k]] + lrank[k];
-                s_keys[p] = key[k];
-                s_vals[p] = val[k];
-            }
-        __syncthreads();
-        const uint32_t n_tile = min((uint32_t)TILE, end - t0);
-        for (uint32_t p = tid; p < n_tile; p += kBS) {
-            const K kk = s_keys[p];
-            const uint32_t d = (uint32_t)(kk >> shift) & mask;
-            const uint32_t g = s_base[d] + p - s_toff[d];
-            kout[g] = kk;
-            vout[g] = s_vals[p];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < DPT; ++q) s_base[tid * DPT + q] += s_run[tid * DPT + q];
-        __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+        const int c = (int)threadIdx.x * 4 + q;
+        if (c < n_seg) tp[c] = ex;
+        ex += v[q];
+    }
+    if (threadIdx.x == 0) {
+        tp[n_seg] = total;
+        *hist_len = total * (uint32_t)R;
     }
 }
 
-static int sort_blocks(uint32_t n_max)
+struct SegTile {
+    int c;            // segment
+    uint32_t t, nt;   // tile index inside the segment, tiles of the segment
+    uint32_t start, end;
+    uint32_t hbase;   // tp[c] * R
+};
+
+template <int R>
+__device__ __forceinline__ bool seg_tile(const uint32_t *seg, const uint32_t *tp, int n_seg,
+                                         SegTile &st)
 {
-    const uint32_t per_block = 8192;
-    uint32_t nb = (n_max + per_block - 1) / per_block;
-    return (int)(nb < 1 ? 1 : (nb > kMaxBlocks ? kMaxBlocks : nb));
+    const uint32_t b = blockIdx.x;
+    if (b >= tp[n_seg]) return false;
+    int lo = 0, hi = n_seg - 1;
+    while (lo < hi) {  // last segment with tp[c] <= b (skips empty segments)
+        const int mid = (lo + hi + 1) >> 1;
+        if (tp[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    st.c = lo;
+    st.t = b - tp[lo];
+    st.nt = tp[lo + 1] - tp[lo];
+    st.start = seg[lo] + st.t * kSegTile;
+    st.end = min(seg[lo + 1], st.start + kSegTile);
+    st.hbase = tp[lo] * R;
+    return true;
 }
 
 template <typename K, int RB>
-static int radix_sort_rb(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t *n_dev,
-                         uint32_t n_max, int bits, const SortTemp &tmp, hipStream_t st)
+__global__ __launch_bounds__(kBS) void k_seg_hist(const K *__restrict__ keys,
+                                                  const uint32_t *__restrict__ seg,
+                                                  const uint32_t *__restrict__ tp, int n_seg,
+                                                  int shift, uint32_t *__restrict__ hist)
 {
-    constexpr int KPT = sizeof(K) == 8 ? 8 : 8;
-    const int nb = sort_blocks(n_max);
+    constexpr int R = 1 << RB;
+    __shared__ uint32_t h[R];
+    SegTile st;
+    if (!seg_tile<R>(seg, tp, n_seg, st)) return;
+    for (int d = threadIdx.x; d < R; d += kBS) h[d] = 0;
+    __syncthreads();
+    for (uint32_t i = st.start + threadIdx.x; i < st.end; i += kBS)
+        atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (uint32_t)(R - 1)], 1u);
+    __syncthreads();
+    for (int d = threadIdx.x; d < R; d += kBS) hist[st.hbase + d * st.nt + st.t] = h[d];
+}
+
+// Wave-private ranking: wave w ranks keys [w*64*KPT, (w+1)*64*KPT) of the
+// tile, 64 at a time, against its own digit counters in LDS (no barrier per
+// step); one barrier then turns the per-wave counts into wave offsets and
+// tile offsets per digit. The tile is reordered by digit in LDS and written
+// out in that order.
+template <typename K, int RB>
+__global__ __launch_bounds__(kBS) void k_seg_scatter(
+    const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__restrict__ kout,
+    uint32_t *__restrict__ vout, const uint32_t *__restrict__ seg,
+    const uint32_t *__restrict__ tp, int n_seg, int shift, const uint32_t *__restrict__ hist,
+    uint32_t seg_key_stride)
+{
+    constexpr int R = 1 << RB;
+    constexpr int DPT = R / kBS;  // digits owned by each thread
+    __shared__ K s_keys[kSegTile];
+    __shared__ uint32_t s_vals[kSegTile];
+    __shared__ uint32_t s_cnt[kWaves][R];
+    __shared__ uint32_t s_toff[R], s_base[R];
+    __shared__ uint32_t s_wave[kWaves];
+    SegTile st;
+    if (!seg_tile<R>(seg, tp, n_seg, st)) return;
+    const uint32_t tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const uint32_t lane = __lane_id();
+    const uint64_t lt = lanemask_lt();
+    const uint32_t mask = (uint32_t)(R - 1);
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+        const int d = tid * DPT + q;
+        s_base[d] = hist[st.hbase + d * st.nt + st.t];
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) s_cnt[w][d] = 0;
+    }
+    __syncthreads();
+    K key[kSegKPT];
+    uint32_t val[kSegKPT], dig[kSegKPT], lrank[kSegKPT];
+    uint32_t *cnt = s_cnt[wave];
+#pragma unroll
+    for (int k = 0; k < kSegKPT; ++k) {
+        const uint32_t i = st.start + (uint32_t)(wave * 64 * kSegKPT + k * 64) + lane;
+        const bool valid = i < st.end;
+        key[k] = 0;
+        val[k] = 0;
+        if (valid) {
+            key[k] = kin[i];
+            val[k] = vin[i];
+        }
+        dig[k] = (uint32_t)(key[k] >> shift) & mask;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < RB; ++bit) {
+            const bool on = (dig[k] >> bit) & 1u;
+            const uint64_t m = __ballot(on);
+            peers &= on ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        const uint32_t before = valid ? cnt[dig[k]] : 0u;
+        lrank[k] = before + rank;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == 0) cnt[dig[k]] = before + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // per digit: offsets of the waves, then exclusive scan of the tile totals
+    {
+        uint32_t tot_d[DPT], sum = 0;
+#pragma unroll
+        for (int q = 0; q < DPT; ++q) {
+            const int d = tid * DPT + q;
+            uint32_t run = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                const uint32_t c = s_cnt[w][d];
+                s_cnt[w][d] = run;
+                run += c;
+            }
+            tot_d[q] = run;
+            sum += run;
+        }
+        uint32_t tot;
+        uint32_t ex = block_excl_scan<kWaves>(sum, tot, s_wave);
+#pragma unroll
+        for (int q = 0; q < DPT; ++q) {
+            s_toff[tid * DPT + q] = ex;
+            ex += tot_d[q];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSegKPT; ++k) {
+        const uint32_t i = st.start + (uint32_t)(wave * 64 * kSegKPT + k * 64) + lane;
+        if (i < st.end) {
+            const uint32_t p = s_toff[dig[k]] + s_cnt[wave][dig[k]] + lrank[k];
+            s_keys[p] = key[k];
+            s_vals[p] = val[k];
+        }
+    }
+    __syncthreads();
+    const uint32_t n_tile = st.end - st.start;
+    const K add = (K)((uint32_t)st.c * seg_key_stride);
+    for (uint32_t p = tid; p < n_tile; p += kBS) {
+        const K kk = s_keys[p];
+        const uint32_t d = (uint32_t)(kk >> shift) & mask;
+        const uint32_t g = s_base[d] + p - s_toff[d];
+        kout[g] = kk + add;
+        vout[g] = s_vals[p];
+    }
+}
+
+template <typename K, int RB>
+static int seg_sort_rb(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t *seg, int n_seg,
+                       uint32_t n_max, int bits, uint32_t stride, const SegSortTemp &tmp,
+                       hipStream_t st)
+{
+    constexpr int R = 1 << RB;
+    const uint32_t max_tiles = (uint32_t)(((uint64_t)n_max + kSegTile - 1) / kSegTile) + (uint32_t)n_seg;
+    hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, st, seg, n_seg, R, tmp.tp,
+                       tmp.hist_len);
     int cur = 0;
     for (int shift = 0; shift < bits; shift += RB) {
         K *ki = cur ? k1 : k0;
         K *ko = cur ? k0 : k1;
         uint32_t *vi = cur ? v1 : v0;
         uint32_t *vo = cur ? v0 : v1;
-        hipLaunchKernelGGL((k_radix_hist<K, RB>), dim3(nb), dim3(kBS), 0, st, ki, n_dev, shift, nb,
-                           tmp.hist);
-        scan_u32(tmp.hist, nullptr, (uint32_t)((1 << RB) * nb), tmp.hist, nullptr, tmp.scan, st);
-        hipLaunchKernelGGL((k_radix_scatter<K, RB, KPT>), dim3(nb), dim3(kBS), 0, st, ki, vi, ko,
-                           vo, n_dev, shift, nb, tmp.hist);
+        hipLaunchKernelGGL((k_seg_hist<K, RB>), dim3(max_tiles), dim3(kBS), 0, st, ki, seg, tmp.tp,
+                           n_seg, shift, tmp.hist);
+        scan_u32(tmp.hist, tmp.hist_len, max_tiles * (uint32_t)R, tmp.hist, nullptr, tmp.scan, st);
+        const uint32_t add = shift + RB >= bits ? stride : 0u;
+        hipLaunchKernelGGL((k_seg_scatter<K, RB>), dim3(max_tiles), dim3(kBS), 0, st, ki, vi, ko,
+                           vo, seg, tmp.tp, n_seg, shift, tmp.hist, add);
         cur ^= 1;
     }
     return cur;
 }
 
-// 10-bit digits when they need fewer passes than 8-bit ones.
-template <typename K>
-static int radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t *n_dev,
-                      uint32_t n_max, int bits, const SortTemp &tmp, hipStream_t st)
+uint64_t seg_sort_hist_entries(uint32_t n_max, int n_seg)
 {
-    if ((bits + 9) / 10 < (bits + 7) / 8)
-        return radix_sort_rb<K, 10>(k0, v0, k1, v1, n_dev, n_max, bits, tmp, st);
-    return radix_sort_rb<K, 8>(k0, v0, k1, v1, n_dev, n_max, bits, tmp, st);
+    return (((uint64_t)n_max + kSegTile - 1) / kSegTile + (uint64_t)n_seg) * 2048u;
 }
 
-int radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, const uint32_t *n_dev,
-                   uint32_t n_max, int bits, const SortTemp &tmp, hipStream_t st)
+int seg_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *seg,
+                 int n_seg, uint32_t n_max, int bits, uint32_t seg_key_stride,
+                 const SegSortTemp &tmp, hipStream_t st)
 {
-    return radix_sort<uint64_t>(k0, v0, k1, v1, n_dev, n_max, bits, tmp, st);
+    if (bits <= 0) return 0;
+    // 11-bit digits carry a histogram entry per key (8-bit ones: one per 8
+    // keys), so they pay only where they at least halve the passes
+    const int p8 = (bits + 7) / 8, p11 = (bits + 10) / 11;
+    if (p8 - p11 >= p11)
+        return seg_sort_rb<uint32_t, 11>(k0, v0, k1, v1, seg, n_seg, n_max, bits, seg_key_stride,
+                                         tmp, st);
+    return seg_sort_rb<uint32_t, 8>(k0, v0, k1, v1, seg, n_seg, n_max, bits, seg_key_stride, tmp,
+                                    st);
 }
 
-int radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *n_dev,
-                   uint32_t n_max, int bits, const SortTemp &tmp, hipStream_t st)
+// ------------------------------------------------- per-camera tile binning --
+// Stable counting sort of one camera's instances by tile, one block per
+// camera. Wave w owns a contiguous part of the camera's segment; pass 1
+// counts its tiles into the wave's own LDS row, the block then turns the rows
+// into per-(wave, tile) output positions (tile-major, waves in order, so the
+// depth order inside a tile is kept) and writes the tile ranges; pass 2 walks
+// the same parts again and writes each value at its position, ranking equal
+// tiles of one 64-wide step with a ballot peer mask.
+constexpr int kBinLds = 20480;  // u32 counters per block (80 KB)
+
+template <int W>
+__global__ __launch_bounds__(W * 64) void k_tile_bin(const uint32_t *__restrict__ ikeys,
+                                                     const uint32_t *__restrict__ ivals,
+                                                     const uint32_t *__restrict__ inst_start,
+                                                     int T, int tbits,
+                                                     uint32_t *__restrict__ ovals,
+                                                     uint2 *__restrict__ ranges)
 {
-    return radix_sort<uint32_t>(k0, v0, k1, v1, n_dev, n_max, bits, tmp, st);
+    __shared__ uint32_t s_cnt[kBinLds];
+    __shared__ uint32_t s_wave[W];
+    const int c = blockIdx.x;
+    const uint32_t a = inst_start[c], b = inst_start[c + 1];
+    const uint32_t n = b - a;
+    const uint32_t per = ((n + W - 1) / W + 63u) & ~63u;
+    const int wave = (int)threadIdx.x >> 6;
+    const uint32_t lane = __lane_id();
+    const uint32_t w0 = min(b, a + (uint32_t)wave * per), w1 = min(b, w0 + per);
+    uint32_t *cnt = s_cnt + wave * T;
+    for (int i = threadIdx.x; i < W * T; i += W * 64) s_cnt[i] = 0;
+    __syncthreads();
+    for (uint32_t i = w0 + lane; i < w1; i += 64) atomicAdd(&cnt[ikeys[i]], 1u);
+    __syncthreads();
+    // thread t owns tiles [t*DPT, t*DPT + DPT)
+    const int DPT = (T + W * 64 - 1) / (W * 64);
+    const int d0 = (int)threadIdx.x * DPT;
+    uint32_t sum = 0;
+    for (int q = 0; q < DPT; ++q) {
+        const int d = d0 + q;
+        if (d < T)
+            for (int w = 0; w < W; ++w) sum += s_cnt[w * T + d];
+    }
+    uint32_t tot;
+    uint32_t ex = a + block_excl_scan<W>(sum, tot, s_wave);
+    for (int q = 0; q < DPT; ++q) {
+        const int d = d0 + q;
+        if (d < T) {
+            const uint32_t start = ex;
+            for (int w = 0; w < W; ++w) {
+                const uint32_t v = s_cnt[w * T + d];
+                s_cnt[w * T + d] = ex;
+                ex += v;
+            }
+            ranges[(uint64_t)c * (uint64_t)T + d] = make_uint2(start, ex);
+        }
+    }
+    __syncthreads();
+    const uint64_t lt = lanemask_lt();
+    for (uint32_t i0 = w0; i0 < w1; i0 += 64) {
+        const uint32_t i = i0 + lane;
+        const bool valid = i < w1;
+        const uint32_t key = valid ? ikeys[i] : 0u;
+        const uint32_t val = valid ? ivals[i] : 0u;
+        uint64_t peers = __ballot(valid);
+        for (int bit = 0; bit < tbits; ++bit) {
+            const bool on = (key >> bit) & 1u;
+            const uint64_t m = __ballot(on);
+            peers &= on ? m : ~m;
+        }
+        const uint32_t before = valid ? cnt[key] : 0u;
+        __builtin_amdgcn_wave_barrier();
+        if (valid) {
+            ovals[before + (uint32_t)__popcll(peers & lt)] = val;
+            if ((peers & lt) == 0ull) cnt[key] = before + (uint32_t)__popcll(peers);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+bool tile_bin_supported(int tiles_per_cam) { return tiles_per_cam >= 1 && tiles_per_cam <= kBinLds; }
+
+void tile_bin(const uint32_t *ikeys, const uint32_t *ivals, const uint32_t *inst_start,
+              int n_cams, int tiles_per_cam, int tbits, uint32_t *ovals, uint2 *ranges,
+              hipStream_t st)
+{
+    const int T = tiles_per_cam;
+    if (n_cams < 1) return;
+#define GS_BIN(W_)                                                                            \
+    if (W_ * T <= kBinLds) {                                                                  \
+        hipLaunchKernelGGL(k_tile_bin<W_>, dim3(n_cams), dim3(W_ * 64), 0, st, ikeys, ivals,  \
+                           inst_start, T, tbits, ovals, ranges);                              \
+        return;                                                                               \
+    }
+    GS_BIN(16) GS_BIN(8) GS_BIN(4) GS_BIN(2) GS_BIN(1)
+#undef GS_BIN
+}
+
+// ------------------------------------------------- per-camera depth sort --
+// Stable LSD sort of one camera's (z bits, slot) records by z, one block per
+// camera, all passes in one launch. The keys are positive floats, so their
+// bit patterns order like the depths; the block first finds the camera's
+// smallest and largest key and sorts key - min, which needs only as many
+// bits as the camera's depth range spans (27 bits cover a depth ratio of
+// 2^16). The digit width is picked so that the pass count is odd, leaving
+// the result in (k1, v1). Each pass: per-wave digit counts in LDS, one scan
+// into per-(wave, digit) positions, then a ranked scatter (ballot peer masks
+// inside each 64-wide step), as in the tile binning.
+constexpr int kCamW = 16;       // waves per block
+constexpr int kCamRMax = 1024;  // largest radix
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = min(v, (uint32_t)__shfl_xor(v, d, 64));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, (uint32_t)__shfl_xor(v, d, 64));
+    return v;
+}
+
+__global__ __launch_bounds__(kCamW * 64) void k_cam_depth_sort(uint32_t *k0, uint32_t *v0,
+                                                               uint32_t *k1, uint32_t *v1,
+                                                               const uint32_t *__restrict__ seg)
+{
+    constexpr int W = kCamW;
+    constexpr int NT = W * 64;
+    __shared__ uint32_t s_cnt[W * kCamRMax];
+    __shared__ uint32_t s_wave[W], s_lo[W], s_hi[W];
+    const int c = blockIdx.x;
+    const uint32_t a = seg[c], b = seg[c + 1];
+    const uint32_t n = b - a;
+    const uint32_t per = ((n + W - 1) / W + 63u) & ~63u;
+    const int tid = (int)threadIdx.x;
+    const int wave = tid >> 6;
+    const uint32_t lane = __lane_id();
+    const uint32_t w0 = min(b, a + (uint32_t)wave * per), w1 = min(b, w0 + per);
+    // key range of the camera
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    for (uint32_t i = a + (uint32_t)tid; i < b; i += NT) {
+        const uint32_t k = k0[i];
+        lo = min(lo, k);
+        hi = max(hi, k);
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if (lane == 0) {
+        s_lo[wave] = lo;
+        s_hi[wave] = hi;
+    }
+    __syncthreads();
+    lo = s_lo[0];
+    hi = s_hi[0];
+#pragma unroll
+    for (int w = 1; w < W; ++w) {
+        lo = min(lo, s_lo[w]);
+        hi = max(hi, s_hi[w]);
+    }
+    const uint32_t span = n > 1 ? hi - lo : 0u;
+    const int bits = span ? 32 - __clz((int)span) : 0;
+    int rb, passes;
+    if (bits <= 9) {
+        rb = bits > 0 ? bits : 1;
+        passes = 1;
+    } else if (bits <= 27) {
+        rb = 9;
+        passes = 3;
+    } else if (bits <= 30) {
+        rb = 10;
+        passes = 3;
+    } else {
+        rb = 7;
+        passes = 5;
+    }
+    const int R = 1 << rb;
+    const uint32_t mask = (uint32_t)(R - 1);
+    uint32_t *cnt = s_cnt + wave * R;
+    const uint64_t lt = lanemask_lt();
+    for (int p = 0; p < passes; ++p) {
+        const uint32_t *ki = (p & 1) ? k1 : k0;
+        const uint32_t *vi = (p & 1) ? v1 : v0;
+        uint32_t *ko = (p & 1) ? k0 : k1;
+        uint32_t *vo = (p & 1) ? v0 : v1;
+        const int shift = p * rb;
+        const bool last = p + 1 == passes;
+        for (int i = tid; i < W * R; i += NT) s_cnt[i] = 0;
+        __syncthreads();
+        for (uint32_t i = w0 + lane; i < w1; i += 64)
+            atomicAdd(&cnt[((ki[i] - lo) >> shift) & mask], 1u);
+        __syncthreads();
+        // thread t owns digit t (R <= NT)
+        uint32_t sum = 0;
+        if (tid < R)
+            for (int w = 0; w < W; ++w) sum += s_cnt[w * R + tid];
+        uint32_t tot;
+        uint32_t ex = a + block_excl_scan<W>(sum, tot, s_wave);
+        if (tid < R)
+            for (int w = 0; w < W; ++w) {
+                const uint32_t v = s_cnt[w * R + tid];
+                s_cnt[w * R + tid] = ex;
+                ex += v;
+            }
+        __syncthreads();
+        for (uint32_t i0 = w0; i0 < w1; i0 += 64) {
+            const uint32_t i = i0 + lane;
+            const bool valid = i < w1;
+            const uint32_t key = valid ? ki[i] : lo;
+            const uint32_t val = valid ? vi[i] : 0u;
+            const uint32_t dig = ((key - lo) >> shift) & mask;
+            uint64_t peers = __ballot(valid);
+            for (int bit = 0; bit < rb; ++bit) {
+                const bool on = (dig >> bit) & 1u;
+                const uint64_t m = __ballot(on);
+                peers &= on ? m : ~m;
+            }
+            const uint32_t before = valid ? cnt[dig] : 0u;
+            __builtin_amdgcn_wave_barrier();
+            if (valid) {
+                const uint32_t pos = before + (uint32_t)__popcll(peers & lt);
+                if (!last) ko[pos] = key;
+                vo[pos] = val;
+                if ((peers & lt) == 0ull) cnt[dig] = before + (uint32_t)__popcll(peers);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        // this pass's stores are read by other waves in the next one
+        __syncthreads();
+    }
+}
+
+void cam_depth_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *seg,
+                    int n_cams, hipStream_t st)
+{
+    if (n_cams < 1) return;
+    hipLaunchKernelGGL(k_cam_depth_sort, dim3(n_cams), dim3(kCamW * 64), 0, st, k0, v0, k1, v1,
+                       seg);
 }
 
 }  // namespace gs

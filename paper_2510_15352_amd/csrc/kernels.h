@@ -25,8 +25,10 @@ struct ScanTemp {
     uint32_t *partial;  // >= 4096 entries
 };
 
-struct SortTemp {
-    uint32_t *hist;  // >= 1024 * 4096 entries (digits x blocks)
+struct SegSortTemp {
+    uint32_t *hist;      // >= seg_sort_hist_entries(n_max, n_seg) entries
+    uint32_t *tp;        // >= n_seg + 1 entries (tiles per segment, scanned)
+    uint32_t *hist_len;  // 1 entry
     ScanTemp scan;
 };
 
@@ -38,7 +40,22 @@ struct RasterArgs {
     int tiles_x, tiles_per_cam, W, H;
     float bg_r, bg_g, bg_b;
     float *rgb, *depth, *alpha;
+    // 0: write the frame. 1, 2: a sub-frame of a blended frame, written (1)
+    // or added (2) as rgb += blend_w * rgb_k, depth += sum of w z (before the
+    // division), alpha += accumulated weight (alpha is then required).
+    int blend;
+    float blend_w;
 };
+
+// Sub-frame camera poses of a motion-blurred frame: for every camera i and
+// sub-frame k < K, the pose with centre C_i - v_i * offs[k] (rotation kept),
+// written as out[k][i][3][4].
+void launch_blur_poses(const float *poses, const float *vel, int n_cams, const float *offs, int K,
+                       float *out, hipStream_t st);
+// Final pass of a blended frame: depth = (sum w z) / (sum of weights), or 0;
+// alpha = (sum of weights) * inv_k.
+void launch_blur_finalize(float *depth, float *alpha_sum, float *alpha_out, int64_t n_px,
+                          float inv_k, hipStream_t st);
 
 void launch_scene_prep(const float *means, const float *scales, const float *quats,
                        const float *opacity, const float *sh, int64_t n, int ncoef, float4 *pos_op,
@@ -56,21 +73,42 @@ void launch_debug_project(const SceneDev &sc, const int32_t *perm, const CamPara
 void scan_u32(const uint32_t *in, const uint32_t *n_dev, uint32_t n_max, uint32_t *out,
               uint32_t *total_out, const ScanTemp &tmp, hipStream_t st);
 // Order-preserving compaction of the set bits of the visibility words into
-// (camera << 31 | z bits, slot) pairs; *n_vis_out receives their number.
+// (z bits, slot) pairs, camera-major; *n_vis_out receives their number and
+// seg_start[c] (c <= n_cams) the first position of camera c.
 void compact_visible(const uint64_t *vis, uint32_t n_words, const uint32_t *cam_slot, int n_cams,
-                     const uint32_t *zbits, uint64_t *keys, uint32_t *vals, uint32_t *n_vis_out,
-                     const ScanTemp &tmp, hipStream_t st);
-// Tile instances of the depth-sorted records: counts[1] = instances,
-// counts[2] = min(instances, cap), flags updated; entries past cap dropped.
-void emit_instances(const uint64_t *dkeys, const uint32_t *dvals, const uint32_t *n_vis,
-                    uint32_t n_max, const uint2 *rect, int tw, int th, int tiles_x,
-                    int tiles_per_cam, uint32_t cap, uint32_t *ikeys, uint32_t *ivals,
-                    uint32_t *counts, RenderFlags *flags, const ScanTemp &tmp, hipStream_t st);
-// Return 0 if the sorted data ended in (k0, v0), 1 if in (k1, v1).
-int radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, const uint32_t *n_dev,
-                   uint32_t n_max, int bits, const SortTemp &tmp, hipStream_t st);
-int radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *n_dev,
-                   uint32_t n_max, int bits, const SortTemp &tmp, hipStream_t st);
+                     const uint32_t *zbits, uint32_t *keys, uint32_t *vals, uint32_t *n_vis_out,
+                     uint32_t *seg_start, const ScanTemp &tmp, hipStream_t st);
+// Tile instances of the depth-sorted records, keyed by the tile index inside
+// the camera: counts[1] = instances, counts[2] = min(instances, cap), flags
+// updated; entries past cap dropped; ioff[i] = first instance of record i;
+// inst_start[c] (c <= n_cams) = first instance of camera c.
+void emit_instances(const uint32_t *dvals, const uint32_t *n_vis, uint32_t n_max,
+                    const uint32_t *vis_start, int n_cams, const uint2 *rect, int tw, int th,
+                    int tiles_x, uint32_t cap, uint32_t *ikeys, uint32_t *ivals, uint32_t *ioff,
+                    uint32_t *inst_start, uint32_t *counts, RenderFlags *flags,
+                    const ScanTemp &tmp, hipStream_t st);
+// Stable sort of u32 keys by their low `bits` bits inside the segments
+// [seg[c], seg[c+1]) (on the device; seg[0] = 0, n_seg <= 4096, the segments
+// tile [0, seg[n_seg]) and seg[n_seg] <= n_max). The last pass adds
+// c * seg_key_stride to the keys of segment c. Returns 0 if the result is in
+// (k0, v0), 1 if in (k1, v1).
+int seg_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *seg,
+                 int n_seg, uint32_t n_max, int bits, uint32_t seg_key_stride,
+                 const SegSortTemp &tmp, hipStream_t st);
+// Stable sort by z bits (positive floats) of each camera's segment
+// [seg[c], seg[c+1]) of (k0, v0); the sorted values land in v1 (k0, k1 and
+// v0 are clobbered).
+void cam_depth_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *seg,
+                    int n_cams, hipStream_t st);
+// Stable sort of each camera's instance segment [inst_start[c],
+// inst_start[c+1]) by tile (keys < tiles_per_cam < 2^tbits): values to ovals,
+// ranges[c * tiles_per_cam + t] = (first, end) of tile t. Needs
+// tile_bin_supported(tiles_per_cam).
+bool tile_bin_supported(int tiles_per_cam);
+void tile_bin(const uint32_t *ikeys, const uint32_t *ivals, const uint32_t *inst_start,
+              int n_cams, int tiles_per_cam, int tbits, uint32_t *ovals, uint2 *ranges,
+              hipStream_t st);
+uint64_t seg_sort_hist_entries(uint32_t n_max, int n_seg);
 
 void launch_finalize_counts(uint32_t *counts, uint32_t cap, RenderFlags *flags, hipStream_t st);
 void launch_zero_u32(uint32_t *p, uint64_t n, hipStream_t st);

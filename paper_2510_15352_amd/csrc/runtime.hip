@@ -106,17 +106,29 @@ struct Lane {
     DevBuf<uint2> rect;
     DevBuf<uint32_t> zbits;
     DevBuf<uint64_t> vis;
-    DevBuf<uint64_t> dkeys[2];
-    DevBuf<uint32_t> dvals[2];
+    DevBuf<uint32_t> dkeys[2], dvals[2];
     DevBuf<uint32_t> ikeys[2], ivals[2];
+    DevBuf<uint32_t> ioff;                // first instance of each depth-sorted record
+    DevBuf<uint32_t> vis_start, inst_start;  // per-camera segment starts (+ end)
     DevBuf<uint2> ranges;
     DevBuf<uint32_t> counts;  // [0] visible, [1] instances, [2] kept
     DevBuf<RenderFlags> flags;
     DevBuf<uint32_t> queue;
-    DevBuf<uint32_t> scan_partial, sort_hist;
+    DevBuf<uint32_t> scan_partial, sort_hist, sort_tp, sort_len;
 };
 
 constexpr int kLanes = 2;
+
+// How the raster stores a frame: as the frame itself, or as sub-frame k of a
+// blended (motion-blurred) frame (mode 1 for the first, 2 for the others).
+struct Blend {
+    int mode = 0;
+    float w = 1.0f;
+};
+constexpr int kMaxChunkCams = 4096;  // segments of one segmented sort
+constexpr int kMaxBlurSub = 16;      // sub-frames of a motion-blurred frame
+// instance buffer entries per chunk: keeps every sort histogram index in 32 bits
+constexpr uint64_t kMaxInstCap = uint64_t(1) << 31;
 
 // Learned upsampler: FP32 master weights [cout][9][32] (layer 1's four input
 // channels zero-padded to 32), Adam moments, BF16 packed copies, buffers.
@@ -162,6 +174,8 @@ struct gs_ctx {
     Lane lanes[kLanes];
     DevBuf<CamParams> cams;
     DevBuf<float> dbg_pose;
+    // motion blur: sub-frame poses, time offsets, summed weights
+    DevBuf<float> blur_poses, blur_offs, blur_asum;
     uint64_t inst_cap = 0;
     int generation = 0;  // bumps whenever a workspace buffer moves
 
@@ -267,8 +281,10 @@ std::string choice_key(const Choice &c)
 // at most `chunk` cameras and ~2^27 visibility slots; each chunk's projection
 // is split into items of 256 Gaussians x up to 16 cameras of one scene.
 std::unique_ptr<Plan> make_plan(gs_ctx *ctx, int n_cams, const int32_t *scene_ids, int W, int H,
-                                const Choice &ch)
+                                const Choice &ch, const std::vector<int32_t> *subset = nullptr)
 {
+    // a subset renders only the listed batch cameras into their own slots
+    if (subset) n_cams = (int)subset->size();
     constexpr int kCamGroup = 16;
     const uint64_t kSlotBudget = uint64_t(1) << 27;
     auto P = std::make_unique<Plan>();
@@ -280,7 +296,7 @@ std::unique_ptr<Plan> make_plan(gs_ctx *ctx, int n_cams, const int32_t *scene_id
     P->tiles_y = (H + ch.th - 1) / ch.th;
     P->tiles_per_cam = P->tiles_x * P->tiles_y;
     P->order.resize(n_cams);
-    for (int i = 0; i < n_cams; ++i) P->order[i] = i;
+    for (int i = 0; i < n_cams; ++i) P->order[i] = subset ? (*subset)[i] : i;
     std::stable_sort(P->order.begin(), P->order.end(),
                      [&](int a, int b) { return scene_ids[a] < scene_ids[b]; });
     P->cam_slot.resize(n_cams);
@@ -328,7 +344,7 @@ std::unique_ptr<Plan> make_plan(gs_ctx *ctx, int n_cams, const int32_t *scene_id
         P->chunks.push_back(c);
     }
     for (int i = 0; i < n_cams; ++i) {
-        const int sid = scene_ids[i];
+        const int sid = scene_ids[P->order[i]];
         if (std::find(P->scenes_used.begin(), P->scenes_used.end(), sid) == P->scenes_used.end())
             P->scenes_used.push_back(sid);
     }
@@ -352,7 +368,7 @@ bool ensure_workspace(gs_ctx *ctx, const Plan &P, int n_lanes)
     bool moved = false;
     const uint64_t slots = std::max<uint64_t>(P.max_slots, 64);
     if (ctx->inst_cap == 0) ctx->inst_cap = std::max<uint64_t>(uint64_t(1) << 20, slots / 2);
-    ctx->inst_cap = std::min<uint64_t>(ctx->inst_cap, uint64_t(0xFFFFFFF0u));
+    ctx->inst_cap = std::min<uint64_t>(ctx->inst_cap, kMaxInstCap);
     for (int l = 0; l < n_lanes; ++l) {
         Lane &L = ctx->lanes[l];
         moved |= L.recA.reserve(slots);
@@ -367,12 +383,19 @@ bool ensure_workspace(gs_ctx *ctx, const Plan &P, int n_lanes)
             moved |= L.ikeys[i].reserve(ctx->inst_cap);
             moved |= L.ivals[i].reserve(ctx->inst_cap);
         }
+        moved |= L.ioff.reserve(slots);
+        moved |= L.vis_start.reserve((uint64_t)P.max_chunk_cams + 1);
+        moved |= L.inst_start.reserve((uint64_t)P.max_chunk_cams + 1);
         moved |= L.ranges.reserve((uint64_t)P.max_chunk_cams * P.tiles_per_cam);
         moved |= L.counts.reserve(4);
         moved |= L.flags.reserve(1);
         moved |= L.queue.reserve(1);
         moved |= L.scan_partial.reserve(4096);
-        moved |= L.sort_hist.reserve(1024 * 4096);
+        moved |= L.sort_hist.reserve(
+            std::max(seg_sort_hist_entries((uint32_t)slots, P.max_chunk_cams),
+                     seg_sort_hist_entries((uint32_t)ctx->inst_cap, P.max_chunk_cams)));
+        moved |= L.sort_tp.reserve((uint64_t)P.max_chunk_cams + 1);
+        moved |= L.sort_len.reserve(1);
     }
     moved |= ctx->cams.reserve(std::max(P.n_cams, 1));
     if (moved) ++ctx->generation;
@@ -419,7 +442,7 @@ struct StageTimer {
 void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float *intr, float near,
                     const float bg[3], float *rgb, float *depth, float *alpha, hipStream_t st,
                     hipStream_t aux, int n_lanes, StageTimer *tm = nullptr,
-                    bool count_pairs = false)
+                    bool count_pairs = false, Blend blend = Blend{})
 {
     StageTimer off{ctx, st, false};
     StageTimer &T = tm ? *tm : off;
@@ -443,7 +466,7 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
         const hipStream_t s = (ci % n_lanes) ? aux : st;
         T.st = s;
         ScanTemp scan{L.scan_partial.p};
-        SortTemp sort{L.sort_hist.p, scan};
+        SegSortTemp sort{L.sort_hist.p, L.sort_tp.p, L.sort_len.p, scan};
         const CamParams *cams = ctx->cams.p + c.start;
         const uint32_t *cam_slot = P.d_cam_slot.p + c.start;
         const uint32_t n_words = (uint32_t)(c.slots / 64);
@@ -454,34 +477,46 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
                                cam_slot, near, P.W, P.H, L.recA.p, L.recB.p, L.recC.p, L.rect.p,
                                L.zbits.p, L.vis.p, s);
         T.end(GS_STAGE_PROJECT, t0);
-        // visible count and order-preserving compaction
+        // visible count, order-preserving compaction, per-camera segments
         t0 = T.begin();
         compact_visible(L.vis.p, n_words, cam_slot, c.count, L.zbits.p, L.dkeys[0].p,
-                        L.dvals[0].p, L.counts.p + 0, scan, s);
+                        L.dvals[0].p, L.counts.p + 0, L.vis_start.p, scan, s);
         T.end(GS_STAGE_COMPACT, t0);
-        // depth sort: key = (camera << 31) | z bits (z > 0, sign bit clear)
-        const int dbits = 31 + bits_for((uint64_t)c.count);
+        // depth sort inside each camera's segment: key = z bits (z > 0)
         t0 = T.begin();
-        const int r = radix_sort_u64(L.dkeys[0].p, L.dvals[0].p, L.dkeys[1].p, L.dvals[1].p,
-                                     L.counts.p + 0, (uint32_t)c.slots, dbits, sort, s);
+        cam_depth_sort(L.dkeys[0].p, L.dvals[0].p, L.dkeys[1].p, L.dvals[1].p, L.vis_start.p,
+                       c.count, s);
+        const int r = 1;
         T.end(GS_STAGE_DEPTH_SORT, t0);
-        // tile instances in (camera, depth, index) order
+        // tile instances in (camera, depth, index) order, keyed by tile
         t0 = T.begin();
-        emit_instances(L.dkeys[r].p, L.dvals[r].p, L.counts.p + 0, (uint32_t)c.slots, L.rect.p,
-                       ch.tw, ch.th, P.tiles_x, P.tiles_per_cam, cap, L.ikeys[0].p, L.ivals[0].p,
-                       L.counts.p, L.flags.p, scan, s);
+        emit_instances(L.dvals[r].p, L.counts.p + 0, (uint32_t)c.slots, L.vis_start.p, c.count,
+                       L.rect.p, ch.tw, ch.th, P.tiles_x, cap, L.ikeys[0].p, L.ivals[0].p,
+                       L.ioff.p, L.inst_start.p, L.counts.p, L.flags.p, scan, s);
         T.end(GS_STAGE_EMIT, t0);
-        // stable tile sort keeps the depth order inside each tile
+        // stable sort by tile inside each camera keeps the depth order in
+        // each tile
         const uint64_t n_tiles = (uint64_t)c.count * P.tiles_per_cam;
-        t0 = T.begin();
-        const int r2 = radix_sort_u32(L.ikeys[0].p, L.ivals[0].p, L.ikeys[1].p, L.ivals[1].p,
-                                      L.counts.p + 2, cap, std::max(1, bits_for(n_tiles)), sort,
-                                      s);
-        T.end(GS_STAGE_TILE_SORT, t0);
-        t0 = T.begin();
-        launch_zero_u32((uint32_t *)L.ranges.p, n_tiles * 2, s);
-        launch_ranges(L.ikeys[r2].p, L.counts.p + 2, L.ranges.p, cap, s);
-        T.end(GS_STAGE_RANGES, t0);
+        const int tbits = std::max(1, bits_for((uint64_t)P.tiles_per_cam));
+        int r2 = 1;
+        if (tile_bin_supported(P.tiles_per_cam)) {
+            t0 = T.begin();
+            tile_bin(L.ikeys[0].p, L.ivals[0].p, L.inst_start.p, c.count, P.tiles_per_cam, tbits,
+                     L.ivals[1].p, L.ranges.p, s);
+            T.end(GS_STAGE_TILE_SORT, t0);
+        } else {
+            // more tiles than one block's counters: radix passes, whose last
+            // one turns the keys into camera * tiles + tile, then the ranges
+            t0 = T.begin();
+            r2 = seg_sort_u32(L.ikeys[0].p, L.ivals[0].p, L.ikeys[1].p, L.ivals[1].p,
+                              L.inst_start.p, c.count, cap, tbits, (uint32_t)P.tiles_per_cam, sort,
+                              s);
+            T.end(GS_STAGE_TILE_SORT, t0);
+            t0 = T.begin();
+            launch_zero_u32((uint32_t *)L.ranges.p, n_tiles * 2, s);
+            launch_ranges(L.ikeys[r2].p, L.counts.p + 2, L.ranges.p, cap, s);
+            T.end(GS_STAGE_RANGES, t0);
+        }
         RasterArgs a;
         a.ranges = L.ranges.p;
         a.ivals = L.ivals[r2].p;
@@ -499,6 +534,8 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
         a.rgb = rgb;
         a.depth = depth;
         a.alpha = alpha;
+        a.blend = blend.mode;
+        a.blend_w = blend.w;
         t0 = T.begin();
         launch_raster(ch.tw, ch.th, ch.batch, ch.persistent != 0, a, c.count, L.queue.p,
                       persistent_blocks, count_pairs ? L.flags.p : nullptr, s);
@@ -563,12 +600,19 @@ int check_scene_ids(gs_ctx *ctx, int n_cams, const int32_t *scene_ids, uint64_t 
 std::string graph_key(int n_cams, const int32_t *scene_ids, int W, int H, const Choice &ch,
                       float near, const float *bg, const void *poses, const void *intr,
                       const void *rgb, const void *depth, const void *alpha, int generation,
-                      uint64_t cap)
+                      uint64_t cap, const std::vector<int32_t> *subset)
 {
     uint64_t h = 1469598103934665603ull;
     for (int i = 0; i < n_cams; ++i) {
         h ^= (uint32_t)scene_ids[i];
         h *= 1099511628211ull;
+    }
+    if (subset) {
+        h ^= 0x5bd1e995u;
+        for (int32_t c : *subset) {
+            h ^= (uint32_t)c + 1u;
+            h *= 1099511628211ull;
+        }
     }
     char b[512];
     snprintf(b, sizeof b, "%d|%llx|%dx%d|%s|%a|%a,%a,%a|%p|%p|%p|%p|%p|g%d|c%llu", n_cams,
@@ -579,15 +623,18 @@ std::string graph_key(int n_cams, const int32_t *scene_ids, int W, int H, const 
 
 int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const float *poses,
                 const float *intr, int32_t W, int32_t H, float *rgb, float *depth, float *alpha,
-                const gs_render_opts &o, hipStream_t st, const Choice *forced)
+                const gs_render_opts &o, hipStream_t st, const Choice *forced,
+                const std::vector<int32_t> *subset = nullptr, Blend blend = Blend{})
 {
     uint64_t total = 0;
     int rc = check_scene_ids(ctx, n_cams, scene_ids, &total);
     if (rc) return rc;
-    Choice ch = forced ? *forced : resolve_choice(ctx, o, n_cams, W, H, total);
+    const int n_render = subset ? (int)subset->size() : n_cams;
+    Choice ch = forced ? *forced : resolve_choice(ctx, o, n_render, W, H, total);
     if (!raster_supported(ch.tw, ch.th, ch.batch))
         return fail(ctx, GS_ERR_INVALID_ARG, "unsupported tile/batch choice " + choice_key(ch));
-    if (ch.chunk < 1) return fail(ctx, GS_ERR_INVALID_ARG, "chunk_cams must be >= 1");
+    if (ch.chunk < 1 || ch.chunk > kMaxChunkCams)
+        return fail(ctx, GS_ERR_INVALID_ARG, "chunk_cams must be in [1, 4096]");
     const bool batched = o.mode != GS_MODE_PLAIN;
     const bool use_graph = batched && o.use_graph;
     // two lanes (overlapped chunk pipelines) for batched renders, except when
@@ -601,30 +648,34 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
         DevFlags f;
         if (!use_graph) {
             // eager: the plain form is the same kernel sequence with one camera per chunk
-            std::unique_ptr<Plan> P = make_plan(ctx, n_cams, scene_ids, W, H, ch);
+            std::unique_ptr<Plan> P = make_plan(ctx, n_cams, scene_ids, W, H, ch, subset);
             if (ensure_workspace(ctx, *P, n_lanes)) clear_graphs(ctx);
             enqueue_render(ctx, *P, poses, intr, o.near_plane, o.bg, rgb, depth, alpha, st,
-                           ctx->aux_stream, n_lanes, &timer, o.count_pairs != 0);
+                           ctx->aux_stream, n_lanes, &timer, o.count_pairs != 0, blend);
             read_flags(ctx, n_lanes, st, f);
         } else {
+            const std::string tail = "|l" + std::to_string(n_lanes) + "|b" +
+                                     std::to_string(blend.mode) + ":" + std::to_string(blend.w);
             std::string key = graph_key(n_cams, scene_ids, W, H, ch, o.near_plane, o.bg, poses,
-                                        intr, rgb, depth, alpha, ctx->generation, ctx->inst_cap) +
-                              "|l" + std::to_string(n_lanes);
+                                        intr, rgb, depth, alpha, ctx->generation, ctx->inst_cap,
+                                        subset) +
+                              tail;
             auto it = ctx->graphs.find(key);
             if (it == ctx->graphs.end()) {
                 auto g = std::make_unique<GraphEntry>();
-                g->plan = make_plan(ctx, n_cams, scene_ids, W, H, ch);
+                g->plan = make_plan(ctx, n_cams, scene_ids, W, H, ch, subset);
                 if (ensure_workspace(ctx, *g->plan, n_lanes)) {
                     clear_graphs(ctx);
                     key = graph_key(n_cams, scene_ids, W, H, ch, o.near_plane, o.bg, poses, intr,
-                                    rgb, depth, alpha, ctx->generation, ctx->inst_cap) +
-                          "|l" + std::to_string(n_lanes);
+                                    rgb, depth, alpha, ctx->generation, ctx->inst_cap, subset) +
+                          tail;
                 }
                 HIP_CHECK(hipStreamBeginCapture(ctx->capture_stream,
                                                 hipStreamCaptureModeThreadLocal));
                 try {
                     enqueue_render(ctx, *g->plan, poses, intr, o.near_plane, o.bg, rgb, depth,
-                                   alpha, ctx->capture_stream, ctx->capture_aux, n_lanes);
+                                   alpha, ctx->capture_stream, ctx->capture_aux, n_lanes, nullptr,
+                                   false, blend);
                 } catch (...) {
                     hipGraph_t junk = nullptr;
                     (void)hipStreamEndCapture(ctx->capture_stream, &junk);
@@ -652,9 +703,9 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
         ++regrows;
         uint64_t want = std::max<uint64_t>((uint64_t)f.max_inst + f.max_inst / 4 + 1024,
                                            ctx->inst_cap * 2);
-        if (want > 0xFFFFFFF0ull) want = 0xFFFFFFF0ull;
+        if (want > kMaxInstCap) want = kMaxInstCap;
         if (want <= ctx->inst_cap)
-            return fail(ctx, GS_ERR_CAPACITY, "instance count exceeds the 32-bit index range");
+            return fail(ctx, GS_ERR_CAPACITY, "instance count per chunk exceeds 2^31");
         ctx->inst_cap = want;
         clear_graphs(ctx);
         if (attempt == 5) return fail(ctx, GS_ERR_CAPACITY, "instance buffers kept overflowing");
@@ -721,11 +772,9 @@ void up_zero_state(gs_ctx *ctx)
     U.packed = false;
 }
 
-// Parameter vector (oracle layout) -> FP32 master weights.
-void up_set(gs_ctx *ctx, const float *params)
+// Parameter-vector layout (host) -> padded FP32 device tensors.
+void up_put(DevBuf<float> *wdst, DevBuf<float> *bdst, const float *params)
 {
-    Upsampler &U = ctx->up;
-    up_zero_state(ctx);
     const float *src = params;
     for (int l = 0; l < 4; ++l) {
         const int ci = kUpCin[l], co = kUpCout[l];
@@ -734,10 +783,18 @@ void up_set(gs_ctx *ctx, const float *params)
             for (int t = 0; t < 9; ++t)
                 for (int c = 0; c < ci; ++c) w[((size_t)o * 9 + t) * kUpCinM + c] = src[((size_t)o * 9 + t) * ci + c];
         src += (size_t)co * 9 * ci;
-        HIP_CHECK(hipMemcpy(U.w[l].p, w.data(), w.size() * 4, hipMemcpyHostToDevice));
-        HIP_CHECK(hipMemcpy(U.b[l].p, src, (size_t)co * 4, hipMemcpyHostToDevice));
+        HIP_CHECK(hipMemcpy(wdst[l].p, w.data(), w.size() * 4, hipMemcpyHostToDevice));
+        HIP_CHECK(hipMemcpy(bdst[l].p, src, (size_t)co * 4, hipMemcpyHostToDevice));
         src += co;
     }
+}
+
+// Parameter vector (oracle layout) -> FP32 master weights; Adam reset.
+void up_set(gs_ctx *ctx, const float *params)
+{
+    Upsampler &U = ctx->up;
+    up_zero_state(ctx);
+    up_put(U.w, U.b, params);
     U.ready = true;
 }
 
@@ -1096,6 +1153,115 @@ int gs_render_batch(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const
     });
 }
 
+int gs_render_due(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const float *poses,
+                  const float *intrinsics, int32_t width, int32_t height, int64_t sim_step,
+                  int32_t period, const int32_t *phase, float *rgb, float *depth, float *alpha,
+                  const gs_render_opts *opts, int32_t *n_due_out, void *stream)
+{
+    int rc = validate_render_args(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb,
+                                  depth);
+    if (rc) return rc;
+    if (period < 1) return fail(ctx, GS_ERR_INVALID_ARG, "period must be >= 1");
+    if (sim_step < 0) return fail(ctx, GS_ERR_INVALID_ARG, "sim_step must be >= 0");
+    gs_render_opts o;
+    if (opts) o = *opts; else gs_default_opts(&o);
+    if (o.mode != GS_MODE_PLAIN && o.mode != GS_MODE_BATCHED)
+        return fail(ctx, GS_ERR_INVALID_ARG, "mode must be GS_MODE_PLAIN or GS_MODE_BATCHED");
+    if (!(o.near_plane > 0.0f) || !std::isfinite(o.near_plane))
+        return fail(ctx, GS_ERR_INVALID_ARG, "near_plane must be a positive finite value");
+    // camera i is due when (sim_step + phase_i) is a multiple of the period
+    std::vector<int32_t> due;
+    for (int32_t i = 0; i < n_cams; ++i) {
+        const int64_t ph = phase ? (int64_t)phase[i] : (int64_t)i;
+        if (ph < 0) return fail(ctx, GS_ERR_INVALID_ARG, "phase values must be >= 0");
+        if ((sim_step + ph) % period == 0) due.push_back(i);
+    }
+    if (n_due_out) *n_due_out = (int32_t)due.size();
+    if (due.empty()) {
+        ctx->last = gs_stats{};
+        return GS_OK;
+    }
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        return render_impl(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb, depth,
+                           alpha, o, (hipStream_t)stream, nullptr, &due);
+    });
+}
+
+int gs_render_batch_motion_blur(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids,
+                                const float *poses, const float *velocities,
+                                const float *intrinsics, int32_t width, int32_t height,
+                                float shutter, int32_t n_sub, float *rgb, float *depth,
+                                float *alpha, const gs_render_opts *opts, void *stream)
+{
+    int rc = validate_render_args(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb,
+                                  depth);
+    if (rc) return rc;
+    if (!velocities) return fail(ctx, GS_ERR_INVALID_ARG, "null velocities");
+    if (n_sub < 1 || n_sub > kMaxBlurSub)
+        return fail(ctx, GS_ERR_INVALID_ARG, "n_sub must be in [1, 16]");
+    if (!(shutter >= 0.0f) || !std::isfinite(shutter))
+        return fail(ctx, GS_ERR_INVALID_ARG, "shutter must be a finite value >= 0");
+    gs_render_opts o;
+    if (opts) o = *opts; else gs_default_opts(&o);
+    if (o.mode != GS_MODE_PLAIN && o.mode != GS_MODE_BATCHED)
+        return fail(ctx, GS_ERR_INVALID_ARG, "mode must be GS_MODE_PLAIN or GS_MODE_BATCHED");
+    if (!(o.near_plane > 0.0f) || !std::isfinite(o.near_plane))
+        return fail(ctx, GS_ERR_INVALID_ARG, "near_plane must be a positive finite value");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        const hipStream_t st = (hipStream_t)stream;
+        const int64_t n_px = (int64_t)n_cams * width * height;
+        // sub-frame k sits at the middle of the k-th of n_sub equal parts of
+        // the exposure [t - shutter, t]
+        float offs[kMaxBlurSub];
+        for (int k = 0; k < n_sub; ++k) offs[k] = (float)((double)shutter * (k + 0.5) / n_sub);
+        bool moved = ctx->blur_poses.reserve((size_t)n_sub * n_cams * 12);
+        moved |= ctx->blur_offs.reserve(kMaxBlurSub);
+        float *asum = alpha;
+        if (!alpha) {
+            moved |= ctx->blur_asum.reserve((size_t)n_px);
+            asum = ctx->blur_asum.p;
+        }
+        if (moved) {
+            // graphs captured with the old addresses of these buffers
+            clear_graphs(ctx);
+            ++ctx->generation;
+        }
+        HIP_CHECK(hipMemcpyAsync(ctx->blur_offs.p, offs, sizeof(float) * n_sub,
+                                 hipMemcpyHostToDevice, st));
+        launch_blur_poses(poses, velocities, n_cams, ctx->blur_offs.p, n_sub, ctx->blur_poses.p, st);
+        const float w = 1.0f / (float)n_sub;
+        // an instance-buffer regrow inside a sub-frame re-runs that sub-frame
+        // on top of its partial sums: start the blend over (capacity only
+        // grows, so this ends)
+        int64_t regrows = 0;
+        for (int attempt = 0; attempt < 4; ++attempt) {
+            bool clean = true;
+            for (int k = 0; k < n_sub && clean; ++k) {
+                Blend b;
+                b.mode = k == 0 ? 1 : 2;
+                b.w = w;
+                int r = render_impl(ctx, n_cams, scene_ids, ctx->blur_poses.p + (size_t)k * n_cams * 12,
+                                    intrinsics, width, height, rgb, depth, asum, o, st, nullptr,
+                                    nullptr, b);
+                if (r) return r;
+                if (ctx->last.regrows > 0) {
+                    regrows += ctx->last.regrows;
+                    clean = false;
+                }
+            }
+            if (clean) {
+                launch_blur_finalize(depth, asum, alpha, n_px, w, st);
+                HIP_CHECK(hipGetLastError());
+                ctx->last.regrows = regrows;
+                return GS_OK;
+            }
+        }
+        return fail(ctx, GS_ERR_CAPACITY, "instance buffers kept overflowing");
+    });
+}
+
 int gs_last_stats(gs_ctx *ctx, gs_stats *out)
 {
     if (!ctx || !out) return GS_ERR_INVALID_ARG;
@@ -1106,7 +1272,8 @@ int gs_last_stats(gs_ctx *ctx, gs_stats *out)
 int gs_set_instance_capacity(gs_ctx *ctx, int64_t cap)
 {
     if (!ctx) return GS_ERR_INVALID_ARG;
-    if (cap < 1 || cap > 0xFFFFFFF0ll) return fail(ctx, GS_ERR_INVALID_ARG, "capacity out of range");
+    if (cap < 1 || cap > (int64_t)kMaxInstCap)
+        return fail(ctx, GS_ERR_INVALID_ARG, "capacity out of range [1, 2^31]");
     return guarded(ctx, [&] {
         HIP_CHECK(hipSetDevice(ctx->device));
         HIP_CHECK(hipDeviceSynchronize());
@@ -1310,6 +1477,69 @@ int gs_upsampler_get_weights(gs_ctx *ctx, float *params, int64_t n)
         HIP_CHECK(hipSetDevice(ctx->device));
         HIP_CHECK(hipDeviceSynchronize());
         up_get(ctx, ctx->up.w, ctx->up.b, params);
+        return GS_OK;
+    });
+}
+
+// Checkpoint file: magic, version, parameter count, Adam step, then the
+// parameter vector and Adam's first and second moments in the same layout.
+static const char kUpMagic[8] = {'G', 'S', 'U', 'P', 'C', 'K', 'P', 'T'};
+constexpr uint32_t kUpVersion = 1;
+
+int gs_upsampler_save(gs_ctx *ctx, const char *path)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (!path) return fail(ctx, GS_ERR_INVALID_ARG, "null path");
+    if (!ctx->up.ready) return fail(ctx, GS_ERR_NOT_TRAINED, "upsampler not initialised");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        HIP_CHECK(hipDeviceSynchronize());
+        Upsampler &U = ctx->up;
+        const size_t np = (size_t)up_num_params();
+        std::vector<float> buf(3 * np);
+        up_get(ctx, U.w, U.b, buf.data());
+        up_get(ctx, U.mw, U.mb, buf.data() + np);
+        up_get(ctx, U.vw, U.vb, buf.data() + 2 * np);
+        FILE *f = fopen(path, "wb");
+        if (!f) return fail(ctx, GS_ERR_INVALID_ARG, std::string("cannot open ") + path);
+        const int64_t n64 = (int64_t)np;
+        const int32_t step = U.step, pad = 0;
+        bool ok = fwrite(kUpMagic, 1, 8, f) == 8 && fwrite(&kUpVersion, 4, 1, f) == 1 &&
+                  fwrite(&pad, 4, 1, f) == 1 && fwrite(&n64, 8, 1, f) == 1 &&
+                  fwrite(&step, 4, 1, f) == 1 && fwrite(&pad, 4, 1, f) == 1 &&
+                  fwrite(buf.data(), 4, buf.size(), f) == buf.size();
+        ok = (fclose(f) == 0) && ok;
+        if (!ok) return fail(ctx, GS_ERR_INVALID_ARG, std::string("write failed: ") + path);
+        return GS_OK;
+    });
+}
+
+int gs_upsampler_load(gs_ctx *ctx, const char *path)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (!path) return fail(ctx, GS_ERR_INVALID_ARG, "null path");
+    return guarded(ctx, [&] {
+        FILE *f = fopen(path, "rb");
+        if (!f) return fail(ctx, GS_ERR_INVALID_ARG, std::string("cannot open ") + path);
+        char magic[8];
+        uint32_t version = 0;
+        int32_t pad = 0, step = 0;
+        int64_t n64 = 0;
+        const size_t np = (size_t)up_num_params();
+        std::vector<float> buf(3 * np);
+        bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kUpMagic, 8) == 0 &&
+                  fread(&version, 4, 1, f) == 1 && version == kUpVersion &&
+                  fread(&pad, 4, 1, f) == 1 && fread(&n64, 8, 1, f) == 1 &&
+                  n64 == (int64_t)np && fread(&step, 4, 1, f) == 1 && step >= 0 &&
+                  fread(&pad, 4, 1, f) == 1 && fread(buf.data(), 4, buf.size(), f) == buf.size();
+        fclose(f);
+        if (!ok) return fail(ctx, GS_ERR_INVALID_ARG, std::string("not an upsampler checkpoint: ") + path);
+        HIP_CHECK(hipSetDevice(ctx->device));
+        up_set(ctx, buf.data());
+        Upsampler &U = ctx->up;
+        up_put(U.mw, U.mb, buf.data() + np);
+        up_put(U.vw, U.vb, buf.data() + 2 * np);
+        U.step = step;
         return GS_OK;
     });
 }

@@ -32,7 +32,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = ["Workload", "WORKLOADS", "workload", "scene_sizes", "make_scene",
-           "make_cameras", "camera_trajectories", "tiny_scene"]
+           "make_cameras", "camera_steps", "camera_trajectories", "tiny_scene"]
 
 
 @dataclass(frozen=True)
@@ -196,15 +196,32 @@ def tiny_scene(n: int, seed: int, sh_degree: int = 0, spread: float = 0.6,
 
 # ---------------------------------------------------------------- cameras ----
 
-def look_pose(position, yaw, pitch_down):
-    """Camera-to-world [R | C] (3x4) for OpenCV axes; z-up world frame."""
+def look_poses(positions, yaw, pitch_down):
+    """Camera-to-world [R | C] (m x 3 x 4) for OpenCV axes (x right, y down,
+    z forward); z-up world frame, roll 0."""
+    positions = np.asarray(positions, np.float64).reshape(-1, 3)
+    yaw = np.asarray(yaw, np.float64).reshape(-1)
     cp, sp = math.cos(pitch_down), math.sin(pitch_down)
-    cy_, sy_ = math.cos(yaw), math.sin(yaw)
-    fwd = np.array([cy_ * cp, sy_ * cp, -sp])
-    right = np.array([sy_, -cy_, 0.0])
+    cy_, sy_ = np.cos(yaw), np.sin(yaw)
+    fwd = np.stack([cy_ * cp, sy_ * cp, np.full_like(yaw, -sp)], axis=1)
+    right = np.stack([sy_, -cy_, np.zeros_like(yaw)], axis=1)
     down = np.cross(fwd, right)
-    R = np.stack([right, down, fwd], axis=1)
-    return np.concatenate([R, np.asarray(position, np.float64)[:, None]], axis=1)
+    return np.concatenate([np.stack([right, down, fwd], axis=2), positions[:, :, None]], axis=2)
+
+
+def look_pose(position, yaw, pitch_down):
+    """One camera-to-world pose (3x4), as look_poses."""
+    return look_poses([position], [yaw], pitch_down)[0]
+
+
+def _terrain_poses(k, scene_ids, pos, head):
+    """Poses 0.5 m above each camera's scene heightfield, 15 degrees down."""
+    z = np.empty(len(scene_ids))
+    for s in np.unique(scene_ids):
+        m = scene_ids == s
+        z[m] = heightfield(k, int(s))(pos[m, 0], pos[m, 1]) + 0.5
+    p3 = np.concatenate([pos, z[:, None]], axis=1)
+    return look_poses(p3, head, math.radians(15.0))
 
 
 def camera_trajectories(k: int, n_steps: int):
@@ -259,14 +276,7 @@ def make_cameras(k: int, step: int = 0, subset=None) -> dict:
             P, Hd = camera_trajectories(k, w.traj_steps)
             pick = rng.integers(0, w.traj_steps, size=n)
             pos, head = P[pick, np.arange(n)], Hd[pick, np.arange(n)]
-        hfs = {}
-        for i in range(n):
-            s = int(scene_ids[i])
-            if s not in hfs:
-                hfs[s] = heightfield(k, s)
-            zc = float(hfs[s](pos[i, 0], pos[i, 1])) + 0.5
-            poses[i] = look_pose((pos[i, 0], pos[i, 1], zc), head[i],
-                                 math.radians(15.0))
+        poses = _terrain_poses(k, scene_ids, pos, head)
     out = dict(scene_ids=scene_ids, poses=poses.astype(np.float32),
                intrinsics=intr, width=w.width, height=w.height)
     if subset is not None:
@@ -275,6 +285,19 @@ def make_cameras(k: int, step: int = 0, subset=None) -> dict:
         out["poses"] = out["poses"][idx]
         out["intrinsics"] = out["intrinsics"][idx]
     return out
+
+
+def camera_steps(k: int, n_steps: int) -> dict:
+    """Consecutive sim steps 0..n_steps-1 of workload k's trajectories:
+    poses f32[n_steps, n, 3, 4]; step t equals make_cameras(k, t)."""
+    w = workload(k)
+    base = make_cameras(k, 0)
+    P, Hd = camera_trajectories(k, n_steps)
+    poses = np.empty((n_steps, w.n_cams, 3, 4), np.float32)
+    for t in range(n_steps):
+        poses[t] = _terrain_poses(k, base["scene_ids"], P[t], Hd[t]).astype(np.float32)
+    return dict(scene_ids=base["scene_ids"], poses=poses, intrinsics=base["intrinsics"],
+                width=w.width, height=w.height)
 
 
 def sampled_cameras(k: int, count: int, seed: int) -> dict:
@@ -289,13 +312,7 @@ def sampled_cameras(k: int, count: int, seed: int) -> dict:
     sids = rng.integers(0, w.n_scenes, size=count).astype(np.int32)
     pos = rng.uniform(-lim, lim, size=(count, 2))
     head = rng.uniform(0.0, 2.0 * np.pi, size=count)
-    poses = np.zeros((count, 3, 4), np.float64)
-    hfs = {}
-    for s in np.unique(sids):
-        hfs[int(s)] = heightfield(k, int(s))
-    for i in range(count):
-        zc = float(hfs[int(sids[i])](pos[i, 0], pos[i, 1])) + 0.5
-        poses[i] = look_pose((pos[i, 0], pos[i, 1], zc), head[i], math.radians(15.0))
+    poses = _terrain_poses(k, sids, pos, head)
     intr = np.tile(np.array([w.fx, w.fy, w.cx, w.cy], np.float32), (count, 1))
     return dict(scene_ids=sids, poses=poses.astype(np.float32), intrinsics=intr,
                 width=w.width, height=w.height)

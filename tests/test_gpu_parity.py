@@ -253,6 +253,126 @@ def test_capacity_regrow_path(gpu_renderer, w1):
         assert bool((x == y).all())
 
 
+def test_empty_cameras_between_visible_ones(gpu_renderer, w0):
+    """Cameras with no visible Gaussian leave empty per-camera segments in the
+    depth and tile sorts, here at the start, middle and end of chunks."""
+    sc, sid, cams = w0
+    away = cams["poses"][0].copy()
+    away[:, 2] *= -1
+    away[:, 0] *= -1
+    poses = np.stack([away, cams["poses"][0], away, away, cams["poses"][0], away])
+    intr = np.repeat(cams["intrinsics"][:1], len(poses), axis=0)
+    ref = oracle.render(sc, cams["poses"][0], cams["intrinsics"][0], 64, 48)
+    for chunk in (0, 2, 4):
+        rgb, depth, alpha = gpu_renderer.render([sid] * len(poses), poses, intr, 64, 48,
+                                                chunk_cams=chunk)
+        for c in (1, 4):
+            _check(ref, _np(rgb[c]), _np(depth[c]), _np(alpha[c]), f"chunk {chunk} cam {c}")
+        for c in (0, 2, 3, 5):
+            assert np.all(_np(alpha[c]) == 0) and np.all(_np(depth[c]) == 0)
+
+
+def test_many_tiles_radix_path_matches_oracle(gpu_renderer, w0):
+    """Above 20480 tiles per camera the tile sort leaves the per-camera LDS
+    counting sort for segmented radix passes plus a ranges kernel: 8x8 tiles
+    on a 1296x1040 image (21060 tiles) against the oracle and against the
+    16x16 tiling, bitwise."""
+    sc, sid, cams = w0
+    W, H = 1296, 1040
+    intr = np.array([[900.0, 900.0, W / 2, H / 2]] * 2, np.float32)
+    poses = cams["poses"][:2]
+    small = gpu_renderer.render([sid] * 2, poses, intr, W, H, tile=(8, 8), lds_batch=64)
+    big = gpu_renderer.render([sid] * 2, poses, intr, W, H, tile=(16, 16), lds_batch=256)
+    for x, y in zip(small, big):
+        assert bool((x == y).all())
+    ref = oracle.render(sc, poses[1], intr[1], W, H)
+    _check(ref, _np(small[0][1]), _np(small[1][1]), _np(small[2][1]), "8x8 1296x1040")
+
+
+def test_camera_rate_decimation_renders_due_cameras_only(gpu_renderer, w1):
+    """Over one period every camera is rendered exactly once, bitwise equal
+    to the full render; slots of cameras not due keep their contents."""
+    import torch
+    sc, sid, cams = w1
+    n, period = 13, 5
+    P, K = cams["poses"][:n], cams["intrinsics"][:n]
+    ids = [sid] * n
+    full = gpu_renderer.render(ids, P, K, 640, 480)
+    out = tuple(torch.full_like(t, -7.0) for t in full)
+    seen = np.zeros(n, int)
+    for step in range(period):
+        before = [t.clone() for t in out]
+        nd = gpu_renderer.render_due(ids, P, K, 640, 480, step, period, out, use_graph=(step % 2 == 0))
+        due = [(step + i) % period == 0 for i in range(n)]
+        assert nd == sum(due)
+        for i in range(n):
+            for t_new, t_old, t_full in zip(out, before, full):
+                if due[i]:
+                    assert bool((t_new[i] == t_full[i]).all())
+                else:
+                    assert bool((t_new[i] == t_old[i]).all())
+        seen += due
+    assert np.all(seen == 1)
+    # explicit phases: all cameras due together at steps where step % 3 == 0
+    out2 = tuple(torch.zeros_like(t) for t in full)
+    assert gpu_renderer.render_due(ids, P, K, 640, 480, 4, 3, out2, phase=[2] * n) == n
+    for a, b in zip(out2, full):
+        assert bool((a == b).all())
+    assert gpu_renderer.render_due(ids, P, K, 640, 480, 5, 3, out2, phase=[2] * n) == 0
+
+
+def test_motion_blur_matches_oracle_sub_frames_and_blend(gpu_renderer, w1):
+    """The blurred frame is the blend of its sub-frames: each sub-frame,
+    rendered on its own at the oracle's FP32 sub-pose, matches the oracle,
+    and the blurred output equals the blend of those sub-frames."""
+    sc, sid, cams = w1
+    n, K_sub, shutter = 2, 3, 0.04
+    P, K = cams["poses"][:n], cams["intrinsics"][:n]
+    vel = np.random.default_rng(5).normal(0.0, 2.0, size=(n, 3)).astype(np.float32)
+    rgb, depth, alpha = gpu_renderer.render_motion_blur([sid] * n, P, vel, K, 640, 480,
+                                                        shutter, K_sub)
+    for c in range(n):
+        sub = oracle.blur_subposes(P[c], vel[c], shutter, K_sub)
+        g = gpu_renderer.render([sid] * K_sub, sub, np.repeat(K[c:c + 1], K_sub, axis=0), 640, 480)
+        gr, gd, ga = _np(g[0]), _np(g[1]), _np(g[2])
+        asum = ga.sum(0)
+        np.testing.assert_allclose(_np(rgb[c]), gr.mean(0), atol=2e-6)
+        np.testing.assert_allclose(_np(alpha[c]), asum / K_sub, atol=2e-6)
+        want = np.where(asum > 0, (ga * gd).sum(0) / np.where(asum > 0, asum, 1), 0)
+        np.testing.assert_allclose(_np(depth[c]), want, rtol=2e-5, atol=1e-6)
+        for k in range(K_sub):
+            ref = oracle.render(sc, sub[k], K[c], 640, 480)
+            _check(ref, gr[k], gd[k], ga[k], f"blur cam {c} sub {k}")
+        # and against the oracle's blend directly
+        o_rgb, o_depth, o_alpha, _ = oracle.render_motion_blur(sc, P[c], vel[c], K[c], 640, 480,
+                                                               shutter, K_sub)
+        assert np.abs(_np(rgb[c]) - o_rgb).max() < oracle.RGB_TOL
+        assert np.abs(_np(alpha[c]) - o_alpha).max() < oracle.ALPHA_TOL
+
+
+def test_motion_blur_degenerate_cases(gpu_renderer, w1):
+    """One sub-frame is the plain render bitwise; zero velocity gives the
+    plain render up to the blend's rounding; graph replay equals eager."""
+    sc, sid, cams = w1
+    n = 3
+    P, K = cams["poses"][:n], cams["intrinsics"][:n]
+    vel = np.random.default_rng(6).normal(0.0, 2.0, size=(n, 3)).astype(np.float32)
+    plain = gpu_renderer.render([sid] * n, P, K, 640, 480)
+    one = gpu_renderer.render_motion_blur([sid] * n, P, vel, K, 640, 480, 0.04, 1)
+    for x, y in zip(one, plain):
+        assert bool((x == y).all())
+    still = gpu_renderer.render_motion_blur([sid] * n, P, np.zeros((n, 3)), K, 640, 480, 0.04, 4,
+                                            alpha=False)
+    np.testing.assert_allclose(_np(still[0]), _np(plain[0]), atol=1e-6)
+    np.testing.assert_allclose(_np(still[1]), _np(plain[1]), rtol=1e-5, atol=1e-6)
+    eager = gpu_renderer.render_motion_blur([sid] * n, P, vel, K, 640, 480, 0.04, 4)
+    for _ in range(3):
+        graph = gpu_renderer.render_motion_blur([sid] * n, P, vel, K, 640, 480, 0.04, 4,
+                                                use_graph=True)
+        for x, y in zip(graph, eager):
+            assert bool((x == y).all())
+
+
 # ----------------------------------------------------------- error paths --
 
 def test_error_codes(gpu_renderer, w0):

@@ -127,3 +127,36 @@ def test_training_lowers_loss_and_fallback_paths(gpu_renderer):
     np.testing.assert_allclose(ps, ref, atol=1e-3)
     print("psnr", ps)
     gpu_renderer.release_scene(sid)
+
+
+def test_checkpoint_restores_training_state_exactly(gpu_renderer, tmp_path):
+    """Save after a few Adam steps, load into a second context: the same
+    further steps give bitwise the same weights in both (parameters, both
+    Adam moments and the step count are restored)."""
+    import paper_2510_15352_amd as gs
+    sc = scenegen.tiny_scene(2000, 5, sh_degree=1, spread=1.0)
+    train = scenegen.sampled_cameras(1, 32, seed=3)
+    sid = gpu_renderer.upload_scene(sc)
+    pose = train["poses"].copy()
+    pose[:, :, :3] = np.eye(3, dtype=np.float32)
+    pose[:, :, 3] = np.random.default_rng(0).uniform(-0.3, 0.3, size=(32, 3))
+    pose[:, 2, 3] -= 4.0
+    intr = np.tile(np.array([[80.0, 80.0, 32.0, 24.0]], np.float32), (32, 1))
+    gpu_renderer.up_init(3)
+    gpu_renderer.up_train([sid] * 32, pose, intr, 64, 48, batch=8, steps=4, lr=3e-3)
+    path = str(tmp_path / "up.ckpt")
+    gpu_renderer.up_save(path)
+    gpu_renderer.up_train([sid] * 32, pose, intr, 64, 48, batch=8, steps=3, lr=3e-3)
+    a = gpu_renderer.up_get()
+    other = gs.Renderer(0)
+    try:
+        sid2 = other.upload_scene(sc)
+        other.up_load(path)
+        other.up_train([sid2] * 32, pose, intr, 64, 48, batch=8, steps=3, lr=3e-3)
+        b = other.up_get()
+        with pytest.raises(gs.GsError):
+            other.up_load(str(tmp_path / "missing.ckpt"))
+    finally:
+        other.close()
+    gpu_renderer.release_scene(sid)
+    assert np.array_equal(a, b)

@@ -400,3 +400,53 @@ def test_stop_after_third_of_four():
     np.testing.assert_allclose(r.rgb[24, 32], expect, atol=1e-14)
     w = [a, (1 - a) * a, (1 - a) ** 2 * a]
     assert r.depth[24, 32] == pytest.approx((2 * w[0] + 3 * w[1] + 4 * w[2]) / sum(w), rel=1e-13)
+
+
+# ------------------------------------------------------------ motion blur ----
+
+def test_motion_blur_without_motion_is_the_plain_render():
+    sc = scene_of([[0, 0, 3.0], [0.2, -0.1, 3.5]], [[0.15] * 3, [0.2, 0.1, 0.1]],
+                  [[1, 0, 0, 0]] * 2, [0.7, 0.9], [[0.9, 0.4, 0.1], [0.1, 0.5, 0.8]])
+    intr = [50.0, 50.0, 32.0, 24.0]
+    ref = oracle.render(sc, IDENT_POSE, intr, 64, 48)
+    rgb, depth, alpha, subs = oracle.render_motion_blur(sc, IDENT_POSE, [0, 0, 0], intr, 64, 48,
+                                                        shutter=0.02, n_sub=5)
+    assert len(subs) == 5
+    np.testing.assert_allclose(rgb, ref.rgb, atol=1e-15)
+    np.testing.assert_allclose(depth, ref.depth, rtol=1e-14, atol=1e-15)
+    np.testing.assert_allclose(alpha, ref.alpha, atol=1e-15)
+
+
+def test_motion_blur_single_gaussian_sideways_closed_form():
+    """A camera sliding along its x axis sees one isotropic Gaussian at
+    u_k = fx x_k / z + cx with the off-axis EWA covariance
+    s^2 fx^2 / z^2 (1 + x_k^2 / z^2) + 0.3 along x and s^2 fy^2 / z^2 + 0.3
+    along y: the blurred frame is the mean of those closed-form images, its
+    depth z wherever any sub-frame is covered."""
+    fx, z0, s, o = 50.0, 3.0, 0.12, 0.8
+    sc = scene_of([0, 0, z0], [s, s, s], [1, 0, 0, 0], o, [0.9, 0.4, 0.1])
+    vel, shutter, K = np.array([12.0, 0.0, 0.0]), 0.05, 4
+    intr = [fx, fx, 32.0, 24.0]
+    rgb, depth, alpha, _ = oracle.render_motion_blur(sc, IDENT_POSE, vel, intr, 64, 48,
+                                                     shutter=shutter, n_sub=K)
+    sf = F32(s)
+    imgs, margins = [], []
+    for k in range(K):
+        dt = np.float32(float(np.float32(shutter)) * (k + 0.5) / K)
+        cx_cam = np.float32(0.0) - np.float32(vel[0]) * dt   # camera centre x (FP32 input)
+        x = -float(cx_cam)                                    # Gaussian x in the camera frame
+        var_x = sf * sf * fx * fx / (z0 * z0) * (1 + x * x / (z0 * z0)) + LOWPASS
+        var_y = (fx * sf / z0) ** 2 + LOWPASS
+        img, mar = closed_form_image(fx * x / z0 + 32.0, 24.0, (var_x, 0.0, var_y), F32(o),
+                                     colour_of(sc, 0), z0, 64, 48)
+        imgs.append(img)
+        margins.append(mar)
+    safe = np.min(margins, axis=0) > 1e-9
+    mean = sum(imgs) / K
+    np.testing.assert_allclose(rgb[safe], mean[..., :3][safe], atol=1e-12)
+    np.testing.assert_allclose(alpha[safe], mean[..., 4][safe], atol=1e-12)
+    covered = safe & (mean[..., 4] > 0)
+    np.testing.assert_allclose(depth[covered], z0, rtol=1e-12)
+    assert np.all(depth[safe & (mean[..., 4] == 0)] == 0)
+    # the blur is visible: the covered extent along x exceeds one sub-frame's
+    assert (mean[..., 4] > 0).sum() > (imgs[0][..., 4] > 0).sum() + 10
