@@ -256,7 +256,7 @@ def main():
         # pair counts (instrumented raster, untimed)
         r.render(scene_ids, P, K, W, H, out=out, count_pairs=True)
         sc = r.stats()
-        pairs, evals = sc["pairs_contrib"], sc["pairs_evaluated"]
+        pairs, evals, issued = sc["pairs_contrib"], sc["pairs_evaluated"], sc["pairs_issued"]
         dom = max(per_step, key=per_step.get)
         raster_launch_ms = stage_ms["raster"] / max(stage_n["raster"], 1)
         pairs_per_launch = pairs / max(stage_n["raster"] / args.steps, 1)
@@ -268,10 +268,11 @@ def main():
                     "launches_per_step": stage_n["raster"] / args.steps,
                     "pairs_per_step": pairs, "evaluated_pairs_per_step": evals,
                     "eval_over_contrib": evals / max(pairs, 1),
+                    "issued_lanes_per_step": issued, "issued_over_contrib": issued / max(pairs, 1),
                     "slots_per_pair": SLOTS_PER_PAIR, "dominant_stage": dom,
                     "visible_pairs_per_step": sc["visible"], "instances_per_step": sc["instances"]}
         log(f"raster: {raster_launch_ms:.3f} ms/launch, pairs {pairs:.3e}, evaluated {evals:.3e}, "
-            f"frac {roofline['frac']:.3f}")
+            f"issued lanes {issued:.3e}, frac {roofline['frac']:.3f}")
         # plain form: per-camera kernel sequence
         if args.plain_steps > 0:
             def step_plain():

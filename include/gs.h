@@ -114,7 +114,10 @@ typedef struct {
                                             the raster stage is one kernel launch */
     float stage_ms[GS_N_STAGES];         /* summed HIP-event time per stage (timing renders) */
     int64_t pairs_contrib;   /* (pixel, Gaussian) pairs accumulated (count_pairs renders) */
-    int64_t pairs_evaluated; /* pairs whose alpha the raster evaluated (count_pairs renders) */
+    int64_t pairs_evaluated; /* pairs of still-live pixels whose alpha the raster evaluated
+                                (count_pairs renders) */
+    int64_t pairs_issued;    /* lanes the raster's walk issued: 64 per (wave, record) step,
+                                live pixels or not (count_pairs renders) */
 } gs_stats;
 
 /* sizeof of gs_scene_desc, gs_render_opts and gs_stats as compiled into the

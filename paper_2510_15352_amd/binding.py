@@ -68,7 +68,8 @@ class Stats(ctypes.Structure):
                 ("tile_h", ctypes.c_int32), ("lds_batch", ctypes.c_int32),
                 ("chunk_cams", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("stage_launches", ctypes.c_int32 * 8), ("stage_ms", ctypes.c_float * 8),
-                ("pairs_contrib", ctypes.c_int64), ("pairs_evaluated", ctypes.c_int64)]
+                ("pairs_contrib", ctypes.c_int64), ("pairs_evaluated", ctypes.c_int64),
+                ("pairs_issued", ctypes.c_int64)]
 
 
 _lib = None

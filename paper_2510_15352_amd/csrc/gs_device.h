@@ -192,14 +192,12 @@ __device__ __forceinline__ TileBox tile_box(uint2 r, int tw, int th)
 }
 
 // Can the Gaussian (conic factor ex, ey, fy; threshold tau) reach alpha >=
-// 1/255 at some pixel centre of a rectangle? Tile-local form: the pixels are
-// lx in [x0, x1], ly in [y0, y1] (integers, tile-local), offsets (Xo, Yo) =
-// tile origin + 0.5 - (u, v), as in the LDS form of the compositing step.
-__device__ __forceinline__ bool may_touch_local(float ex, float ey, float fy, float Xo, float Yo,
-                                                float tau, int x0, int x1, int y0, int y1)
+// 1/255 at some pixel centre of a rectangle? The centres are at offsets
+// [X0, X0 + w] x [Y0, Y0 + h] (pixel steps) from the Gaussian's mean.
+__device__ __forceinline__ bool may_touch(float ex, float ey, float fy, float X0, float Y0,
+                                         float w, float h, float tau)
 {
-    return rect_min_q(ex, ey, fy, (float)x0 + Xo, (float)x1 + Xo, (float)y0 + Yo,
-                      (float)y1 + Yo) <= tau;
+    return rect_min_q(ex, ey, fy, X0, X0 + w, Y0, Y0 + h) <= tau;
 }
 
 // EWA projection of one Gaussian into one camera (steps: cull at the near
@@ -299,12 +297,13 @@ struct Pixel {
     float T, r, g, b, zw;
 };
 
-// LDS form of a record for one tile, with (lx, ly) the pixel's position in
-// the tile (integers) and (Xo, Yo) = tile origin + 0.5 - (u, v):
-//   A = (ex, ey, E0, fy), B = (F0, -log2(opacity), r, g), C = (b, z),
-//   E0 = ex Xo + ey Yo, F0 = fy Yo,
-// so that the conic factor terms are e = ex lx + ey ly + E0, f = fy ly + F0
-// and opacity * exp2(-(e^2 + f^2)) = exp2(-(e^2 + f^2 - log2(opacity))).
+// LDS form of a record: R0 = (ex, ey, fy, -log2(opacity)), R1 = (r, g, b, z),
+// and per wave (E0, F0) = (ex Xw + ey Yw, fy Yw) with (Xw, Yw) = the wave's
+// 8x8 block origin + 0.5 - (u, v). For the pixel at (lx, ly) in the block
+// (integers 0..7) the conic factor terms are e = ex lx + ey ly + E0 and
+// f = fy ly + F0, and opacity * exp2(-(e^2 + f^2)) =
+// exp2(-(e^2 + f^2 - log2(opacity))). The blocks form the same 8x8 grid for
+// every tile shape, so a pixel's arithmetic does not depend on the tiling.
 //
 // One step of the walk for one (pixel, Gaussian) pair: alpha clamped to
 // 0.99; skipped below 1/255; the walk stops (without this Gaussian) when the
@@ -313,21 +312,22 @@ struct Pixel {
 // accumulate adds a zero weight, which leaves every sum bitwise unchanged;
 // once stopped, T < 0 makes every later Tn negative, so nothing accumulates.
 // Returns whether the pair was accumulated.
-__device__ __forceinline__ bool composite(Pixel &s, float lx, float ly, float4 A, float4 B,
-                                          float2 C)
+__device__ __forceinline__ bool composite(Pixel &s, float lx, float ly, float4 R0, float4 R1,
+                                          float E0, float F0)
 {
-    const float e = fmaf(A.x, lx, fmaf(A.y, ly, A.z));
-    const float f = fmaf(A.w, ly, B.x);
-    const float q = fmaf(e, e, fmaf(f, f, B.y));
+    const float e = fmaf(R0.x, lx, fmaf(R0.y, ly, E0));
+    const float f = fmaf(R0.z, ly, F0);
+    const float q = fmaf(e, e, fmaf(f, f, R0.w));
     const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(-q));
     const bool hit = alpha >= kAlphaMin;
-    const float Tn = s.T * (1.0f - alpha);
+    const float wt = alpha * s.T;
+    const float Tn = s.T - wt;
     const bool acc = hit & (Tn >= kTMin);
-    const float w = acc ? alpha * s.T : 0.0f;
-    s.r = fmaf(w, B.z, s.r);
-    s.g = fmaf(w, B.w, s.g);
-    s.b = fmaf(w, C.x, s.b);
-    s.zw = fmaf(w, C.y, s.zw);
+    const float w = acc ? wt : 0.0f;
+    s.r = fmaf(w, R1.x, s.r);
+    s.g = fmaf(w, R1.y, s.g);
+    s.b = fmaf(w, R1.z, s.b);
+    s.zw = fmaf(w, R1.w, s.zw);
     s.T = acc ? Tn : (hit ? -fabsf(s.T) : s.T);
     return acc;
 }

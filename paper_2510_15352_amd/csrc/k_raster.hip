@@ -41,53 +41,49 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ ike
 }
 
 // -------------------------------------------------------------- raster --
-// One block per (camera, tile); each wave owns an 8x8 pixel sub-tile, one
-// pixel per lane. Per LDS batch of B records (staged in the tile-local form
-// of the compositing step), every wave first keeps only the records that can
-// reach its 8x8 rectangle (may_touch_local, 64 records per ballot, compacted
-// with mbcnt into a per-wave list of LDS byte offsets), then walks that list
-// front to back. A skipped record has alpha < 1/255 at every pixel of the
-// wave, so the per-pixel result is the same as walking the full tile list.
-// The block stops when a barrier count says every pixel is done.
+// One block per (camera, tile); each wave owns an 8x8 pixel block, one pixel
+// per lane. Per LDS batch of B records, every wave first keeps only the
+// records that can reach its 8x8 rectangle (may_touch, 64 records per
+// ballot, compacted with mbcnt into a per-wave list that also carries the
+// record's block-relative offsets E0, F0), then walks that list front to
+// back. A skipped record has alpha < 1/255 at every pixel of the wave, so the
+// per-pixel result is the same as walking the full tile list. The block
+// stops when a barrier count says every pixel is done.
 template <int TW, int TH, int B, bool COUNT = false>
-__device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &a, float4 *sA,
-                                            float4 *sB, float4 *sC, float *sT, uint32_t *sL,
-                                            RenderFlags *cnt = nullptr)
+__device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &a, float4 *sR,
+                                            uint4 *sL, RenderFlags *cnt = nullptr)
 {
-    static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are made of 8x8 wave sub-tiles");
+    static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are made of 8x8 wave blocks");
     constexpr int NT = TW * TH;
     constexpr int SX = TW / 8;
     const int wave = (int)threadIdx.x >> 6;
     const uint32_t lane = __lane_id();
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    const int ox = tx * TW, oy = ty * TH;
-    // the wave's pixel rectangle in tile-local pixels, clipped to the image
-    const int lx0 = (wave % SX) * 8, ly0 = (wave / SX) * 8;
-    const int lx1 = min(lx0 + 7, a.W - 1 - ox), ly1 = min(ly0 + 7, a.H - 1 - oy);
-    const int lxi = lx0 + (int)(lane & 7u), lyi = ly0 + (int)(lane >> 3);
-    const int pxi = ox + lxi, pyi = oy + lyi;
+    const int wx0 = tx * TW + (wave % SX) * 8, wy0 = ty * TH + (wave / SX) * 8;
+    const int pxi = wx0 + (int)(lane & 7u), pyi = wy0 + (int)(lane >> 3);
     const bool inside = pxi < a.W && pyi < a.H;
-    const float lx = (float)lxi, ly = (float)lyi;
-    const float fox = (float)ox + 0.5f, foy = (float)oy + 0.5f;
+    const float lx = (float)(lane & 7u), ly = (float)(lane >> 3);
+    // the wave's pixel rectangle, clipped to the image (extent in pixels)
+    const float ww = (float)(min(wx0 + 7, a.W - 1) - wx0), wh = (float)(min(wy0 + 7, a.H - 1) - wy0);
+    const float cx0 = (float)wx0 + 0.5f, cy0 = (float)wy0 + 0.5f;
     const uint2 rg = a.ranges[(uint32_t)cl * (uint32_t)a.tiles_per_cam + (uint32_t)tile];
-    uint32_t *list = sL + wave * B;
+    uint4 *list = sL + wave * B;
     const uint64_t lt = lanemask_lt();
-    const char *lds = reinterpret_cast<const char *>(sA);
+    const char *lds = reinterpret_cast<const char *>(sR);
     Pixel s;
     s.T = inside ? 1.0f : -1.0f;
     s.r = 0.0f; s.g = 0.0f; s.b = 0.0f; s.zw = 0.0f;
-    uint32_t n_eval = 0, n_contrib = 0;
+    uint32_t n_eval = 0, n_contrib = 0, n_issue = 0;
     for (uint32_t base = rg.x; base < rg.y; base += B) {
         const int cnt_b = (int)min((uint32_t)B, rg.y - base);
         __syncthreads();
+        // R0 = (ex, ey, fy, -log2 o), R1 = (r, g, b, z), R2 = (u, v, tau)
         for (int j = (int)threadIdx.x; j < cnt_b; j += NT) {
             const uint32_t slot = a.ivals[base + j];
             const float4 A = a.recA[slot], Bv = a.recB[slot], C = a.recC[slot];
-            const float Xo = fox - A.x, Yo = foy - A.y;
-            sA[j] = make_float4(A.z, A.w, fmaf(A.z, Xo, A.w * Yo), Bv.x);
-            sB[j] = make_float4(Bv.x * Yo, -__builtin_amdgcn_logf(Bv.y), Bv.z, Bv.w);
-            sC[j] = make_float4(C.x, C.y, Xo, Yo);
-            sT[j] = C.z;
+            sR[j] = make_float4(A.z, A.w, Bv.x, -__builtin_amdgcn_logf(Bv.y));
+            sR[B + j] = make_float4(Bv.z, Bv.w, C.x, C.y);
+            sR[2 * B + j] = make_float4(A.x, A.y, C.z, 0.0f);
         }
         __syncthreads();
         int n = 0;
@@ -95,34 +91,40 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
             for (int c0 = 0; c0 < cnt_b; c0 += 64) {
                 const int j = c0 + (int)lane;
                 bool hit = false;
+                float E0 = 0.0f, F0 = 0.0f;
                 if (j < cnt_b) {
-                    const float4 A = sA[j], C = sC[j];
-                    hit = may_touch_local(A.x, A.y, A.w, C.z, C.w, sT[j], lx0, lx1, ly0, ly1);
+                    const float4 R0 = sR[j], R2 = sR[2 * B + j];
+                    const float Xw = cx0 - R2.x, Yw = cy0 - R2.y;
+                    hit = may_touch(R0.x, R0.y, R0.z, Xw, Yw, ww, wh, R2.z);
+                    E0 = fmaf(R0.x, Xw, R0.y * Yw);
+                    F0 = R0.z * Yw;
                 }
                 const uint64_t m = __ballot(hit);
-                if (hit) list[n + __popcll(m & lt)] = (uint32_t)j * 16u;
+                if (hit)
+                    list[n + __popcll(m & lt)] =
+                        make_uint4((uint32_t)j * 16u, __float_as_uint(E0), __float_as_uint(F0), 0u);
                 n += __popcll(m);
             }
         }
         __syncthreads();  // per-wave lists written before they are read
         if (__ballot(s.T > 0.0f) != 0ull) {
-            // four list entries per step (one 16-byte LDS read), a wave-level
-            // completion test after each step, then the remainder one by one
+            // four list entries per step, a wave-level completion test after
+            // each step, then the remainder one by one
             int k = 0;
             bool live = true;
             for (; k + 4 <= n; k += 4) {
-                const uint4 jj = *reinterpret_cast<const uint4 *>(list + k);
-                const uint32_t off[4] = {jj.x, jj.y, jj.z, jj.w};
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const float4 A = *reinterpret_cast<const float4 *>(lds + off[u]);
-                    const float4 Bv = *reinterpret_cast<const float4 *>(lds + B * 16 + off[u]);
-                    const float2 C = *reinterpret_cast<const float2 *>(lds + 2 * B * 16 + off[u]);
+                    const uint4 e = list[k + u];
+                    const float4 R0 = *reinterpret_cast<const float4 *>(lds + e.x);
+                    const float4 R1 = *reinterpret_cast<const float4 *>(lds + B * 16 + e.x);
                     if (COUNT) {
                         n_eval += s.T > 0.0f;
-                        n_contrib += composite(s, lx, ly, A, Bv, C);
+                        ++n_issue;
+                        n_contrib += composite(s, lx, ly, R0, R1, __uint_as_float(e.y),
+                                               __uint_as_float(e.z));
                     } else {
-                        composite(s, lx, ly, A, Bv, C);
+                        composite(s, lx, ly, R0, R1, __uint_as_float(e.y), __uint_as_float(e.z));
                     }
                 }
                 if (__ballot(s.T > 0.0f) == 0ull) {
@@ -131,15 +133,16 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
                 }
             }
             for (; live && k < n; ++k) {
-                const uint32_t o = list[k];
-                const float4 A = *reinterpret_cast<const float4 *>(lds + o);
-                const float4 Bv = *reinterpret_cast<const float4 *>(lds + B * 16 + o);
-                const float2 C = *reinterpret_cast<const float2 *>(lds + 2 * B * 16 + o);
+                const uint4 e = list[k];
+                const float4 R0 = *reinterpret_cast<const float4 *>(lds + e.x);
+                const float4 R1 = *reinterpret_cast<const float4 *>(lds + B * 16 + e.x);
                 if (COUNT) {
                     n_eval += s.T > 0.0f;
-                    n_contrib += composite(s, lx, ly, A, Bv, C);
+                    ++n_issue;
+                    n_contrib += composite(s, lx, ly, R0, R1, __uint_as_float(e.y),
+                                           __uint_as_float(e.z));
                 } else {
-                    composite(s, lx, ly, A, Bv, C);
+                    composite(s, lx, ly, R0, R1, __uint_as_float(e.y), __uint_as_float(e.z));
                 }
             }
         }
@@ -147,14 +150,16 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
     }
     if (COUNT) {
         // one atomic per wave
-        uint64_t e = n_eval, c = n_contrib;
+        uint64_t e = n_eval, c = n_contrib, is = n_issue;
         for (int d = 32; d > 0; d >>= 1) {
             e += __shfl_down(e, d, 64);
             c += __shfl_down(c, d, 64);
+            is += __shfl_down(is, d, 64);
         }
         if (lane == 0) {
             atomicAdd(&cnt->pairs_eval, (unsigned long long)e);
             atomicAdd(&cnt->pairs_contrib, (unsigned long long)c);
+            atomicAdd(&cnt->pairs_issued, (unsigned long long)is);
         }
     }
     if (inside) {
@@ -185,27 +190,36 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
     }
 }
 
-// sA, sB, sC are consecutive (the walk addresses them from sA's base).
-#define GS_RASTER_SHARED                                        \
-    __shared__ float4 sRec[3 * B];                              \
-    __shared__ float sT[B];                                     \
-    __shared__ __attribute__((aligned(16))) uint32_t sL[(TW * TH / 64) * B]; \
-    float4 *sA = sRec, *sB = sRec + B, *sC = sRec + 2 * B;
+// records R0, R1, R2 (B each); one list of B entries per wave
+#define GS_RASTER_SHARED                  \
+    __shared__ float4 sR[3 * B];          \
+    __shared__ uint4 sL[(TW * TH / 64) * B];
+
+// Grid forms: one block per (camera, tile) item, item = block index.
+__device__ __forceinline__ uint32_t xcd_item() { return blockIdx.x; }
 
 template <int TW, int TH, int B>
-__global__ __launch_bounds__(TW *TH) void k_raster(RasterArgs a)
+__global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void k_raster(RasterArgs a, uint32_t n_items)
 {
     GS_RASTER_SHARED
-    raster_tile<TW, TH, B>((int)blockIdx.y, (int)blockIdx.x, a, sA, sB, sC, sT, sL);
+    const uint32_t item = xcd_item();
+    if (item >= n_items) return;
+    raster_tile<TW, TH, B>((int)(item / (uint32_t)a.tiles_per_cam),
+                           (int)(item % (uint32_t)a.tiles_per_cam), a, sR, sL);
 }
 
 // Instrumented grid form: same per-pixel arithmetic, plus counts of
 // evaluated and accumulated (pixel, Gaussian) pairs.
 template <int TW, int TH, int B>
-__global__ __launch_bounds__(TW *TH) void k_raster_count(RasterArgs a, RenderFlags *cnt)
+__global__ __launch_bounds__(TW *TH) void k_raster_count(RasterArgs a, uint32_t n_items,
+                                                         RenderFlags *cnt)
 {
     GS_RASTER_SHARED
-    raster_tile<TW, TH, B, true>((int)blockIdx.y, (int)blockIdx.x, a, sA, sB, sC, sT, sL, cnt);
+    const uint32_t item = xcd_item();
+    if (item >= n_items) return;
+    raster_tile<TW, TH, B, true>((int)(item / (uint32_t)a.tiles_per_cam),
+                                 (int)(item % (uint32_t)a.tiles_per_cam), a, sR, sL, cnt);
 }
 
 // Persistent form: a grid sized to the resident capacity pulls
@@ -223,7 +237,7 @@ __global__ __launch_bounds__(TW *TH) void k_raster_persistent(RasterArgs a, uint
         __syncthreads();
         if (item >= n_items) break;
         raster_tile<TW, TH, B>((int)(item / (uint32_t)a.tiles_per_cam),
-                               (int)(item % (uint32_t)a.tiles_per_cam), a, sA, sB, sC, sT, sL);
+                               (int)(item % (uint32_t)a.tiles_per_cam), a, sR, sL);
     }
 }
 
@@ -240,11 +254,13 @@ __global__ void k_blur_poses(const float *__restrict__ poses, const float *__res
     const float dt = offs[k];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
+        // separately rounded product and difference: no fused multiply-add
+#pragma clang fp contract(off)
         o[r * 4 + 0] = p[r * 4 + 0];
         o[r * 4 + 1] = p[r * 4 + 1];
         o[r * 4 + 2] = p[r * 4 + 2];
-        // separately rounded product and difference (no contraction)
-        o[r * 4 + 3] = __fsub_rn(p[r * 4 + 3], __fmul_rn(vel[(int64_t)i * 3 + r], dt));
+        const float step = vel[(int64_t)i * 3 + r] * dt;
+        o[r * 4 + 3] = p[r * 4 + 3] - step;
     }
 }
 
@@ -300,8 +316,8 @@ void launch_ranges(const uint32_t *ikeys, const uint32_t *n_dev, uint2 *ranges, 
 #define GS_RASTER_CASES(X) \
     X(16, 16, 64) X(16, 16, 128) X(16, 16, 256) \
     X(32, 8, 64) X(32, 8, 128) X(32, 8, 256) \
-    X(8, 8, 64) X(16, 8, 64) X(16, 8, 128) \
-    X(32, 16, 128) X(32, 16, 256)
+    X(8, 8, 64) X(8, 8, 128) X(16, 8, 64) X(16, 8, 128) \
+    X(32, 16, 64) X(32, 16, 128)
 
 bool raster_supported(int tw, int th, int b)
 {
@@ -331,11 +347,12 @@ void launch_raster(int tw, int th, int b, bool persistent, const RasterArgs &a, 
 {
     const int tiles = a.tiles_per_cam;
     const uint32_t n_items = (uint32_t)tiles * (uint32_t)n_cams;
+    const uint32_t grid = n_items;
 #define X(TW_, TH_, B_)                                                                          \
     if (tw == TW_ && th == TH_ && b == B_) {                                                     \
         if (count) {                                                                             \
-            hipLaunchKernelGGL((k_raster_count<TW_, TH_, B_>), dim3(tiles, n_cams),             \
-                               dim3(TW_ * TH_), 0, st, a, count);                                \
+            hipLaunchKernelGGL((k_raster_count<TW_, TH_, B_>), dim3(grid), dim3(TW_ * TH_), 0,  \
+                               st, a, n_items, count);                                           \
         } else if (persistent) {                                                                 \
             launch_zero_u32(queue, 1, st);                                                       \
             int blocks = persistent_blocks;                                                      \
@@ -344,8 +361,8 @@ void launch_raster(int tw, int th, int b, bool persistent, const RasterArgs &a, 
             hipLaunchKernelGGL((k_raster_persistent<TW_, TH_, B_>), dim3(blocks),               \
                                dim3(TW_ * TH_), 0, st, a, queue, n_items);                       \
         } else {                                                                                 \
-            hipLaunchKernelGGL((k_raster<TW_, TH_, B_>), dim3(tiles, n_cams), dim3(TW_ * TH_), 0, \
-                               st, a);                                                           \
+            hipLaunchKernelGGL((k_raster<TW_, TH_, B_>), dim3(grid), dim3(TW_ * TH_), 0, st, a,  \
+                               n_items);                                                         \
         }                                                                                        \
         return;                                                                                  \
     }

@@ -392,12 +392,21 @@ struct SegTile {
     uint32_t hbase;   // tp[c] * R
 };
 
+// Blocks are dealt to the 8 XCDs round-robin (block i -> XCD i mod 8). Of
+// the `total` tiles, XCD x takes the contiguous run [x * per, (x + 1) * per),
+// per = ceil(total / 8), so whole segments are written through one XCD's L2
+// (their scattered output lines are completed there) while every XCD gets
+// the same number of tiles. The grid is a multiple of 8 and >= total.
 template <int R>
 __device__ __forceinline__ bool seg_tile(const uint32_t *seg, const uint32_t *tp, int n_seg,
                                          SegTile &st)
 {
-    const uint32_t b = blockIdx.x;
-    if (b >= tp[n_seg]) return false;
+    const uint32_t total = tp[n_seg];
+    const uint32_t per = (total + 7u) >> 3;
+    const uint32_t j = blockIdx.x >> 3;
+    if (j >= per) return false;
+    const uint32_t b = (blockIdx.x & 7u) * per + j;
+    if (b >= total) return false;
     int lo = 0, hi = n_seg - 1;
     while (lo < hi) {  // last segment with tp[c] <= b (skips empty segments)
         const int mid = (lo + hi + 1) >> 1;
@@ -545,7 +554,8 @@ static int seg_sort_rb(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t 
                        hipStream_t st)
 {
     constexpr int R = 1 << RB;
-    const uint32_t max_tiles = (uint32_t)(((uint64_t)n_max + kSegTile - 1) / kSegTile) + (uint32_t)n_seg;
+    const uint32_t max_tiles =
+        ((uint32_t)(((uint64_t)n_max + kSegTile - 1) / kSegTile) + (uint32_t)n_seg + 7u) & ~7u;
     hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, st, seg, n_seg, R, tmp.tp,
                        tmp.hist_len);
     int cur = 0;
@@ -567,7 +577,7 @@ static int seg_sort_rb(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t 
 
 uint64_t seg_sort_hist_entries(uint32_t n_max, int n_seg)
 {
-    return (((uint64_t)n_max + kSegTile - 1) / kSegTile + (uint64_t)n_seg) * 2048u;
+    return (((uint64_t)n_max + kSegTile - 1) / kSegTile + (uint64_t)n_seg + 7u) * 2048u;
 }
 
 int seg_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *seg,
@@ -679,150 +689,6 @@ void tile_bin(const uint32_t *ikeys, const uint32_t *ivals, const uint32_t *inst
     }
     GS_BIN(16) GS_BIN(8) GS_BIN(4) GS_BIN(2) GS_BIN(1)
 #undef GS_BIN
-}
-
-// ------------------------------------------------- per-camera depth sort --
-// Stable LSD sort of one camera's (z bits, slot) records by z, one block per
-// camera, all passes in one launch. The keys are positive floats, so their
-// bit patterns order like the depths; the block first finds the camera's
-// smallest and largest key and sorts key - min, which needs only as many
-// bits as the camera's depth range spans (27 bits cover a depth ratio of
-// 2^16). The digit width is picked so that the pass count is odd, leaving
-// the result in (k1, v1). Each pass: per-wave digit counts in LDS, one scan
-// into per-(wave, digit) positions, then a ranked scatter (ballot peer masks
-// inside each 64-wide step), as in the tile binning.
-constexpr int kCamW = 16;       // waves per block
-constexpr int kCamRMax = 1024;  // largest radix
-
-__device__ __forceinline__ uint32_t wave_min(uint32_t v)
-{
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v = min(v, (uint32_t)__shfl_xor(v, d, 64));
-    return v;
-}
-
-__device__ __forceinline__ uint32_t wave_max(uint32_t v)
-{
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v = max(v, (uint32_t)__shfl_xor(v, d, 64));
-    return v;
-}
-
-__global__ __launch_bounds__(kCamW * 64) void k_cam_depth_sort(uint32_t *k0, uint32_t *v0,
-                                                               uint32_t *k1, uint32_t *v1,
-                                                               const uint32_t *__restrict__ seg)
-{
-    constexpr int W = kCamW;
-    constexpr int NT = W * 64;
-    __shared__ uint32_t s_cnt[W * kCamRMax];
-    __shared__ uint32_t s_wave[W], s_lo[W], s_hi[W];
-    const int c = blockIdx.x;
-    const uint32_t a = seg[c], b = seg[c + 1];
-    const uint32_t n = b - a;
-    const uint32_t per = ((n + W - 1) / W + 63u) & ~63u;
-    const int tid = (int)threadIdx.x;
-    const int wave = tid >> 6;
-    const uint32_t lane = __lane_id();
-    const uint32_t w0 = min(b, a + (uint32_t)wave * per), w1 = min(b, w0 + per);
-    // key range of the camera
-    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
-    for (uint32_t i = a + (uint32_t)tid; i < b; i += NT) {
-        const uint32_t k = k0[i];
-        lo = min(lo, k);
-        hi = max(hi, k);
-    }
-    lo = wave_min(lo);
-    hi = wave_max(hi);
-    if (lane == 0) {
-        s_lo[wave] = lo;
-        s_hi[wave] = hi;
-    }
-    __syncthreads();
-    lo = s_lo[0];
-    hi = s_hi[0];
-#pragma unroll
-    for (int w = 1; w < W; ++w) {
-        lo = min(lo, s_lo[w]);
-        hi = max(hi, s_hi[w]);
-    }
-    const uint32_t span = n > 1 ? hi - lo : 0u;
-    const int bits = span ? 32 - __clz((int)span) : 0;
-    int rb, passes;
-    if (bits <= 9) {
-        rb = bits > 0 ? bits : 1;
-        passes = 1;
-    } else if (bits <= 27) {
-        rb = 9;
-        passes = 3;
-    } else if (bits <= 30) {
-        rb = 10;
-        passes = 3;
-    } else {
-        rb = 7;
-        passes = 5;
-    }
-    const int R = 1 << rb;
-    const uint32_t mask = (uint32_t)(R - 1);
-    uint32_t *cnt = s_cnt + wave * R;
-    const uint64_t lt = lanemask_lt();
-    for (int p = 0; p < passes; ++p) {
-        const uint32_t *ki = (p & 1) ? k1 : k0;
-        const uint32_t *vi = (p & 1) ? v1 : v0;
-        uint32_t *ko = (p & 1) ? k0 : k1;
-        uint32_t *vo = (p & 1) ? v0 : v1;
-        const int shift = p * rb;
-        const bool last = p + 1 == passes;
-        for (int i = tid; i < W * R; i += NT) s_cnt[i] = 0;
-        __syncthreads();
-        for (uint32_t i = w0 + lane; i < w1; i += 64)
-            atomicAdd(&cnt[((ki[i] - lo) >> shift) & mask], 1u);
-        __syncthreads();
-        // thread t owns digit t (R <= NT)
-        uint32_t sum = 0;
-        if (tid < R)
-            for (int w = 0; w < W; ++w) sum += s_cnt[w * R + tid];
-        uint32_t tot;
-        uint32_t ex = a + block_excl_scan<W>(sum, tot, s_wave);
-        if (tid < R)
-            for (int w = 0; w < W; ++w) {
-                const uint32_t v = s_cnt[w * R + tid];
-                s_cnt[w * R + tid] = ex;
-                ex += v;
-            }
-        __syncthreads();
-        for (uint32_t i0 = w0; i0 < w1; i0 += 64) {
-            const uint32_t i = i0 + lane;
-            const bool valid = i < w1;
-            const uint32_t key = valid ? ki[i] : lo;
-            const uint32_t val = valid ? vi[i] : 0u;
-            const uint32_t dig = ((key - lo) >> shift) & mask;
-            uint64_t peers = __ballot(valid);
-            for (int bit = 0; bit < rb; ++bit) {
-                const bool on = (dig >> bit) & 1u;
-                const uint64_t m = __ballot(on);
-                peers &= on ? m : ~m;
-            }
-            const uint32_t before = valid ? cnt[dig] : 0u;
-            __builtin_amdgcn_wave_barrier();
-            if (valid) {
-                const uint32_t pos = before + (uint32_t)__popcll(peers & lt);
-                if (!last) ko[pos] = key;
-                vo[pos] = val;
-                if ((peers & lt) == 0ull) cnt[dig] = before + (uint32_t)__popcll(peers);
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
-        // this pass's stores are read by other waves in the next one
-        __syncthreads();
-    }
-}
-
-void cam_depth_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *seg,
-                    int n_cams, hipStream_t st)
-{
-    if (n_cams < 1) return;
-    hipLaunchKernelGGL(k_cam_depth_sort, dim3(n_cams), dim3(kCamW * 64), 0, st, k0, v0, k1, v1,
-                       seg);
 }
 
 }  // namespace gs

@@ -19,6 +19,7 @@ struct RenderFlags {
     unsigned long long instances;
     unsigned long long pairs_contrib;  // filled by the counting raster only
     unsigned long long pairs_eval;
+    unsigned long long pairs_issued;
 };
 
 struct ScanTemp {
@@ -95,11 +96,6 @@ void emit_instances(const uint32_t *dvals, const uint32_t *n_vis, uint32_t n_max
 int seg_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *seg,
                  int n_seg, uint32_t n_max, int bits, uint32_t seg_key_stride,
                  const SegSortTemp &tmp, hipStream_t st);
-// Stable sort by z bits (positive floats) of each camera's segment
-// [seg[c], seg[c+1]) of (k0, v0); the sorted values land in v1 (k0, k1 and
-// v0 are clobbered).
-void cam_depth_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *seg,
-                    int n_cams, hipStream_t st);
 // Stable sort of each camera's instance segment [inst_start[c],
 // inst_start[c+1]) by tile (keys < tiles_per_cam < 2^tbits): values to ovals,
 // ranges[c * tiles_per_cam + t] = (first, end) of tile t. Needs

@@ -75,7 +75,7 @@ struct Scene {
 using DevFlags = RenderFlags;
 
 struct Choice {
-    int tw = 16, th = 16, batch = 256, chunk = 512, persistent = 0;
+    int tw = 16, th = 16, batch = 128, chunk = 512, persistent = 0;
 };
 
 struct Chunk {
@@ -484,9 +484,8 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
         T.end(GS_STAGE_COMPACT, t0);
         // depth sort inside each camera's segment: key = z bits (z > 0)
         t0 = T.begin();
-        cam_depth_sort(L.dkeys[0].p, L.dvals[0].p, L.dkeys[1].p, L.dvals[1].p, L.vis_start.p,
-                       c.count, s);
-        const int r = 1;
+        const int r = seg_sort_u32(L.dkeys[0].p, L.dvals[0].p, L.dkeys[1].p, L.dvals[1].p,
+                                   L.vis_start.p, c.count, (uint32_t)c.slots, 31, 0u, sort, s);
         T.end(GS_STAGE_DEPTH_SORT, t0);
         // tile instances in (camera, depth, index) order, keyed by tile
         t0 = T.begin();
@@ -564,6 +563,7 @@ void read_flags(gs_ctx *ctx, int n_lanes, hipStream_t st, DevFlags &out)
         out.instances += f.instances;
         out.pairs_contrib += f.pairs_contrib;
         out.pairs_eval += f.pairs_eval;
+        out.pairs_issued += f.pairs_issued;
     }
 }
 
@@ -697,6 +697,7 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
         ctx->last.instances = (int64_t)f.instances;
         ctx->last.pairs_contrib = (int64_t)f.pairs_contrib;
         ctx->last.pairs_evaluated = (int64_t)f.pairs_eval;
+        ctx->last.pairs_issued = (int64_t)f.pairs_issued;
         timer.collect(ctx->last);
         if (!f.overflow) break;
         // grow the instance buffers past the largest chunk's need and retry

@@ -75,7 +75,7 @@ def test_autotuner_choice_is_used_and_bitwise_identical(gpu_renderer):
     ids = [sid] * 32
     P, K = cams["poses"][:32], cams["intrinsics"][:32]
     base = [t.cpu().numpy() for t in gpu_renderer.render(ids, P, K, 640, 480, tile=(16, 16),
-                                                         lds_batch=256, persistent=0)]
+                                                         lds_batch=128, persistent=0)]
     gpu_renderer.autotune(ids, P, K, 640, 480)
     got = gpu_renderer.render(ids, P, K, 640, 480)
     st = gpu_renderer.stats()

@@ -110,7 +110,7 @@ def test_workload1_plain_equals_batched_bitwise(gpu_renderer, w1):
 
 @pytest.mark.parametrize("tile,batch,persistent", [((16, 16), 64, 0), ((32, 8), 128, 1),
                                                    ((8, 8), 64, 0), ((16, 8), 128, 1),
-                                                   ((32, 16), 256, 0), ((16, 16), 256, 1)])
+                                                   ((32, 16), 64, 0), ((16, 16), 256, 1)])
 def test_every_tile_choice_is_bitwise_identical(gpu_renderer, w1, tile, batch, persistent):
     sc, sid, cams = w1
     idx = np.arange(0, 64, 4)
@@ -280,9 +280,10 @@ def test_many_tiles_radix_path_matches_oracle(gpu_renderer, w0):
     sc, sid, cams = w0
     W, H = 1296, 1040
     intr = np.array([[900.0, 900.0, W / 2, H / 2]] * 2, np.float32)
-    poses = cams["poses"][:2]
+    poses = np.repeat(cams["poses"][:1], 2, axis=0)
+    poses[1, :, 3] += (0.3, -0.2, 0.5)
     small = gpu_renderer.render([sid] * 2, poses, intr, W, H, tile=(8, 8), lds_batch=64)
-    big = gpu_renderer.render([sid] * 2, poses, intr, W, H, tile=(16, 16), lds_batch=256)
+    big = gpu_renderer.render([sid] * 2, poses, intr, W, H, tile=(16, 16), lds_batch=128)
     for x, y in zip(small, big):
         assert bool((x == y).all())
     ref = oracle.render(sc, poses[1], intr[1], W, H)
@@ -351,15 +352,21 @@ def test_motion_blur_matches_oracle_sub_frames_and_blend(gpu_renderer, w1):
 
 
 def test_motion_blur_degenerate_cases(gpu_renderer, w1):
-    """One sub-frame is the plain render bitwise; zero velocity gives the
+    """One sub-frame is the plain render at the mid-exposure pose, bitwise
+    (and at the unmoved pose for a zero shutter); zero velocity gives the
     plain render up to the blend's rounding; graph replay equals eager."""
     sc, sid, cams = w1
     n = 3
     P, K = cams["poses"][:n], cams["intrinsics"][:n]
     vel = np.random.default_rng(6).normal(0.0, 2.0, size=(n, 3)).astype(np.float32)
     plain = gpu_renderer.render([sid] * n, P, K, 640, 480)
+    mid = np.stack([oracle.blur_subposes(P[c], vel[c], 0.04, 1)[0] for c in range(n)])
+    plain_mid = gpu_renderer.render([sid] * n, mid, K, 640, 480)
     one = gpu_renderer.render_motion_blur([sid] * n, P, vel, K, 640, 480, 0.04, 1)
-    for x, y in zip(one, plain):
+    for x, y in zip(one, plain_mid):
+        assert bool((x == y).all())
+    zero = gpu_renderer.render_motion_blur([sid] * n, P, vel, K, 640, 480, 0.0, 1)
+    for x, y in zip(zero, plain):
         assert bool((x == y).all())
     still = gpu_renderer.render_motion_blur([sid] * n, P, np.zeros((n, 3)), K, 640, 480, 0.04, 4,
                                             alpha=False)
