@@ -452,7 +452,7 @@ __global__ __launch_bounds__(kBS) void k_seg_scatter(
     uint32_t seg_key_stride)
 {
     constexpr int R = 1 << RB;
-    constexpr int DPT = R / kBS;  // digits owned by each thread
+    constexpr int DPT = R >= kBS ? R / kBS : 1;  // digits owned by each thread
     __shared__ K s_keys[kSegTile];
     __shared__ uint32_t s_vals[kSegTile];
     __shared__ uint32_t s_cnt[kWaves][R];
@@ -468,9 +468,11 @@ __global__ __launch_bounds__(kBS) void k_seg_scatter(
 #pragma unroll
     for (int q = 0; q < DPT; ++q) {
         const int d = tid * DPT + q;
-        s_base[d] = hist[st.hbase + d * st.nt + st.t];
+        if (d < R) {
+            s_base[d] = hist[st.hbase + d * st.nt + st.t];
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) s_cnt[w][d] = 0;
+            for (int w = 0; w < kWaves; ++w) s_cnt[w][d] = 0;
+        }
     }
     __syncthreads();
     K key[kSegKPT];
@@ -509,11 +511,13 @@ __global__ __launch_bounds__(kBS) void k_seg_scatter(
         for (int q = 0; q < DPT; ++q) {
             const int d = tid * DPT + q;
             uint32_t run = 0;
+            if (d < R) {
 #pragma unroll
-            for (int w = 0; w < kWaves; ++w) {
-                const uint32_t c = s_cnt[w][d];
-                s_cnt[w][d] = run;
-                run += c;
+                for (int w = 0; w < kWaves; ++w) {
+                    const uint32_t c = s_cnt[w][d];
+                    s_cnt[w][d] = run;
+                    run += c;
+                }
             }
             tot_d[q] = run;
             sum += run;
@@ -522,7 +526,7 @@ __global__ __launch_bounds__(kBS) void k_seg_scatter(
         uint32_t ex = block_excl_scan<kWaves>(sum, tot, s_wave);
 #pragma unroll
         for (int q = 0; q < DPT; ++q) {
-            s_toff[tid * DPT + q] = ex;
+            if (tid * DPT + q < R) s_toff[tid * DPT + q] = ex;
             ex += tot_d[q];
         }
     }
@@ -577,7 +581,7 @@ static int seg_sort_rb(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t 
 
 uint64_t seg_sort_hist_entries(uint32_t n_max, int n_seg)
 {
-    return (((uint64_t)n_max + kSegTile - 1) / kSegTile + (uint64_t)n_seg + 7u) * 2048u;
+    return (((uint64_t)n_max + kSegTile - 1) / kSegTile + (uint64_t)n_seg + 7u) * 256u;
 }
 
 int seg_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *seg,
@@ -585,110 +589,27 @@ int seg_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const u
                  const SegSortTemp &tmp, hipStream_t st)
 {
     if (bits <= 0) return 0;
-    // 11-bit digits carry a histogram entry per key (8-bit ones: one per 8
-    // keys), so they pay only where they at least halve the passes
-    const int p8 = (bits + 7) / 8, p11 = (bits + 10) / 11;
-    if (p8 - p11 >= p11)
-        return seg_sort_rb<uint32_t, 11>(k0, v0, k1, v1, seg, n_seg, n_max, bits, seg_key_stride,
-                                         tmp, st);
-    return seg_sort_rb<uint32_t, 8>(k0, v0, k1, v1, seg, n_seg, n_max, bits, seg_key_stride, tmp,
-                                    st);
-}
-
-// ------------------------------------------------- per-camera tile binning --
-// Stable counting sort of one camera's instances by tile, one block per
-// camera. Wave w owns a contiguous part of the camera's segment; pass 1
-// counts its tiles into the wave's own LDS row, the block then turns the rows
-// into per-(wave, tile) output positions (tile-major, waves in order, so the
-// depth order inside a tile is kept) and writes the tile ranges; pass 2 walks
-// the same parts again and writes each value at its position, ranking equal
-// tiles of one 64-wide step with a ballot peer mask.
-constexpr int kBinLds = 20480;  // u32 counters per block (80 KB)
-
-template <int W>
-__global__ __launch_bounds__(W * 64) void k_tile_bin(const uint32_t *__restrict__ ikeys,
-                                                     const uint32_t *__restrict__ ivals,
-                                                     const uint32_t *__restrict__ inst_start,
-                                                     int T, int tbits,
-                                                     uint32_t *__restrict__ ovals,
-                                                     uint2 *__restrict__ ranges)
-{
-    __shared__ uint32_t s_cnt[kBinLds];
-    __shared__ uint32_t s_wave[W];
-    const int c = blockIdx.x;
-    const uint32_t a = inst_start[c], b = inst_start[c + 1];
-    const uint32_t n = b - a;
-    const uint32_t per = ((n + W - 1) / W + 63u) & ~63u;
-    const int wave = (int)threadIdx.x >> 6;
-    const uint32_t lane = __lane_id();
-    const uint32_t w0 = min(b, a + (uint32_t)wave * per), w1 = min(b, w0 + per);
-    uint32_t *cnt = s_cnt + wave * T;
-    for (int i = threadIdx.x; i < W * T; i += W * 64) s_cnt[i] = 0;
-    __syncthreads();
-    for (uint32_t i = w0 + lane; i < w1; i += 64) atomicAdd(&cnt[ikeys[i]], 1u);
-    __syncthreads();
-    // thread t owns tiles [t*DPT, t*DPT + DPT)
-    const int DPT = (T + W * 64 - 1) / (W * 64);
-    const int d0 = (int)threadIdx.x * DPT;
-    uint32_t sum = 0;
-    for (int q = 0; q < DPT; ++q) {
-        const int d = d0 + q;
-        if (d < T)
-            for (int w = 0; w < W; ++w) sum += s_cnt[w * T + d];
+    // as many 8-bit passes as needed, with the bits spread evenly over them
+    // (narrower digits: fewer ballots per rank, longer runs per write)
+    const int passes = (bits + 7) / 8;
+    const int rb = (bits + passes - 1) / passes;
+    switch (rb) {
+    case 1: case 2: case 3: case 4:
+        return seg_sort_rb<uint32_t, 4>(k0, v0, k1, v1, seg, n_seg, n_max, bits, seg_key_stride,
+                                        tmp, st);
+    case 5:
+        return seg_sort_rb<uint32_t, 5>(k0, v0, k1, v1, seg, n_seg, n_max, bits, seg_key_stride,
+                                        tmp, st);
+    case 6:
+        return seg_sort_rb<uint32_t, 6>(k0, v0, k1, v1, seg, n_seg, n_max, bits, seg_key_stride,
+                                        tmp, st);
+    case 7:
+        return seg_sort_rb<uint32_t, 7>(k0, v0, k1, v1, seg, n_seg, n_max, bits, seg_key_stride,
+                                        tmp, st);
+    default:
+        return seg_sort_rb<uint32_t, 8>(k0, v0, k1, v1, seg, n_seg, n_max, bits, seg_key_stride,
+                                        tmp, st);
     }
-    uint32_t tot;
-    uint32_t ex = a + block_excl_scan<W>(sum, tot, s_wave);
-    for (int q = 0; q < DPT; ++q) {
-        const int d = d0 + q;
-        if (d < T) {
-            const uint32_t start = ex;
-            for (int w = 0; w < W; ++w) {
-                const uint32_t v = s_cnt[w * T + d];
-                s_cnt[w * T + d] = ex;
-                ex += v;
-            }
-            ranges[(uint64_t)c * (uint64_t)T + d] = make_uint2(start, ex);
-        }
-    }
-    __syncthreads();
-    const uint64_t lt = lanemask_lt();
-    for (uint32_t i0 = w0; i0 < w1; i0 += 64) {
-        const uint32_t i = i0 + lane;
-        const bool valid = i < w1;
-        const uint32_t key = valid ? ikeys[i] : 0u;
-        const uint32_t val = valid ? ivals[i] : 0u;
-        uint64_t peers = __ballot(valid);
-        for (int bit = 0; bit < tbits; ++bit) {
-            const bool on = (key >> bit) & 1u;
-            const uint64_t m = __ballot(on);
-            peers &= on ? m : ~m;
-        }
-        const uint32_t before = valid ? cnt[key] : 0u;
-        __builtin_amdgcn_wave_barrier();
-        if (valid) {
-            ovals[before + (uint32_t)__popcll(peers & lt)] = val;
-            if ((peers & lt) == 0ull) cnt[key] = before + (uint32_t)__popcll(peers);
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
-}
-
-bool tile_bin_supported(int tiles_per_cam) { return tiles_per_cam >= 1 && tiles_per_cam <= kBinLds; }
-
-void tile_bin(const uint32_t *ikeys, const uint32_t *ivals, const uint32_t *inst_start,
-              int n_cams, int tiles_per_cam, int tbits, uint32_t *ovals, uint2 *ranges,
-              hipStream_t st)
-{
-    const int T = tiles_per_cam;
-    if (n_cams < 1) return;
-#define GS_BIN(W_)                                                                            \
-    if (W_ * T <= kBinLds) {                                                                  \
-        hipLaunchKernelGGL(k_tile_bin<W_>, dim3(n_cams), dim3(W_ * 64), 0, st, ikeys, ivals,  \
-                           inst_start, T, tbits, ovals, ranges);                              \
-        return;                                                                               \
-    }
-    GS_BIN(16) GS_BIN(8) GS_BIN(4) GS_BIN(2) GS_BIN(1)
-#undef GS_BIN
 }
 
 }  // namespace gs

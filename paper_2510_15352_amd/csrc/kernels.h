@@ -96,14 +96,6 @@ void emit_instances(const uint32_t *dvals, const uint32_t *n_vis, uint32_t n_max
 int seg_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *seg,
                  int n_seg, uint32_t n_max, int bits, uint32_t seg_key_stride,
                  const SegSortTemp &tmp, hipStream_t st);
-// Stable sort of each camera's instance segment [inst_start[c],
-// inst_start[c+1]) by tile (keys < tiles_per_cam < 2^tbits): values to ovals,
-// ranges[c * tiles_per_cam + t] = (first, end) of tile t. Needs
-// tile_bin_supported(tiles_per_cam).
-bool tile_bin_supported(int tiles_per_cam);
-void tile_bin(const uint32_t *ikeys, const uint32_t *ivals, const uint32_t *inst_start,
-              int n_cams, int tiles_per_cam, int tbits, uint32_t *ovals, uint2 *ranges,
-              hipStream_t st);
 uint64_t seg_sort_hist_entries(uint32_t n_max, int n_seg);
 
 void launch_finalize_counts(uint32_t *counts, uint32_t cap, RenderFlags *flags, hipStream_t st);

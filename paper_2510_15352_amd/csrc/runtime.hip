@@ -497,25 +497,17 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
         // each tile
         const uint64_t n_tiles = (uint64_t)c.count * P.tiles_per_cam;
         const int tbits = std::max(1, bits_for((uint64_t)P.tiles_per_cam));
-        int r2 = 1;
-        if (tile_bin_supported(P.tiles_per_cam)) {
-            t0 = T.begin();
-            tile_bin(L.ikeys[0].p, L.ivals[0].p, L.inst_start.p, c.count, P.tiles_per_cam, tbits,
-                     L.ivals[1].p, L.ranges.p, s);
-            T.end(GS_STAGE_TILE_SORT, t0);
-        } else {
-            // more tiles than one block's counters: radix passes, whose last
-            // one turns the keys into camera * tiles + tile, then the ranges
-            t0 = T.begin();
-            r2 = seg_sort_u32(L.ikeys[0].p, L.ivals[0].p, L.ikeys[1].p, L.ivals[1].p,
-                              L.inst_start.p, c.count, cap, tbits, (uint32_t)P.tiles_per_cam, sort,
-                              s);
-            T.end(GS_STAGE_TILE_SORT, t0);
-            t0 = T.begin();
-            launch_zero_u32((uint32_t *)L.ranges.p, n_tiles * 2, s);
-            launch_ranges(L.ikeys[r2].p, L.counts.p + 2, L.ranges.p, cap, s);
-            T.end(GS_STAGE_RANGES, t0);
-        }
+        // radix passes inside each camera's segment, the last one turning
+        // the keys into camera * tiles + tile, then the ranges
+        t0 = T.begin();
+        const int r2 = seg_sort_u32(L.ikeys[0].p, L.ivals[0].p, L.ikeys[1].p, L.ivals[1].p,
+                                    L.inst_start.p, c.count, cap, tbits, (uint32_t)P.tiles_per_cam,
+                                    sort, s);
+        T.end(GS_STAGE_TILE_SORT, t0);
+        t0 = T.begin();
+        launch_zero_u32((uint32_t *)L.ranges.p, n_tiles * 2, s);
+        launch_ranges(L.ikeys[r2].p, L.counts.p + 2, L.ranges.p, cap, s);
+        T.end(GS_STAGE_RANGES, t0);
         RasterArgs a;
         a.ranges = L.ranges.p;
         a.ivals = L.ivals[r2].p;
