@@ -43,6 +43,40 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+RASTER_SOURCES = ("paper_2510_15352_amd/csrc/k_raster.hip", "paper_2510_15352_amd/csrc/gs_device.h")
+TRAFFIC_PROFILE = "profiles/k_raster_workload2_hbm_traffic.md"
+
+
+def raster_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in RASTER_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed PMC summary, or
+    None when that summary is missing, covers another kernel, or was taken
+    on other raster sources than the ones built now."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel") != kernel or fields.get("sources_sha256") != raster_source_digest():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def gen_workload(k):
     import scenegen
     w = scenegen.workload(k)
@@ -168,7 +202,20 @@ def main():
     ap.add_argument("--train-batch", type=int, default=64)
     ap.add_argument("--calib-cams", type=int, default=512)
     ap.add_argument("--psnr-target", type=float, default=35.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device a few times and exit (reference "
+                         "kernel for scaling the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}))
+        return
     if args.steps is None:
         args.steps = 100 if args.workload == 4 else 5
     if args.gpus != 1:
@@ -261,9 +308,13 @@ def main():
         raster_launch_ms = stage_ms["raster"] / max(stage_n["raster"], 1)
         pairs_per_launch = pairs / max(stage_n["raster"] / args.steps, 1)
         achieved = pairs_per_launch * SLOTS_PER_PAIR / (raster_launch_ms * 1e-3)
-        roofline = {"bound": "alu", "kernel": "k_raster", "achieved": achieved / 1e12,
+        kname = "gs::k_raster<%d, %d, %d>" % (st_graph["tile_w"], st_graph["tile_h"],
+                                              st_graph["lds_batch"])
+        roofline = {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12,
                     "peak": VALU_PEAK / 1e12, "unit": "T VALU lane-ops/s",
-                    "frac": achieved / VALU_PEAK, "traffic": None,
+                    "frac": achieved / VALU_PEAK, "traffic": measured_traffic(kname),
+                    "traffic_unit": "HBM bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, "
+                                    "copy-calibrated)",
                     "avg_launch_ms": raster_launch_ms,
                     "launches_per_step": stage_n["raster"] / args.steps,
                     "pairs_per_step": pairs, "evaluated_pairs_per_step": evals,

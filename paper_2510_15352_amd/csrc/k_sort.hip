@@ -80,14 +80,14 @@ struct LoadPopc {
     __device__ uint32_t operator()(uint32_t i) const { return (uint32_t)__popcll(p[i]); }
 };
 
-// Tiles of the footprint box of the i-th depth-sorted record.
+// Tiles of the footprint box of the i-th depth-sorted record (boxes stored
+// in sorted order by the depth sort's last pass).
 struct LoadTiles {
-    const uint32_t *vals;
     const uint2 *rect;
     int tw, th;
     __device__ uint32_t operator()(uint32_t i) const
     {
-        const TileBox b = tile_box(rect[vals[i]], tw, th);
+        const TileBox b = tile_box(rect[i], tw, th);
         return (uint32_t)(b.bw * b.bh);
     }
 };
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(kBS) void k_emit_down(
         TileBox tb{0, 0, 1, 1};
         if (i < end) {
             slot = dvals[i];
-            tb = tile_box(rect[slot], tw, th);
+            tb = tile_box(rect[i], tw, th);
             kbase = (uint32_t)tb.ty0 * (uint32_t)tiles_x + (uint32_t)tb.tx0;
             cnt = (uint32_t)(tb.bw * tb.bh);
         }
@@ -340,7 +340,7 @@ void emit_instances(const uint32_t *dvals, const uint32_t *n_vis, uint32_t n_max
                     uint32_t *inst_start, uint32_t *counts, RenderFlags *flags,
                     const ScanTemp &tmp, hipStream_t st)
 {
-    const int nb = scan_reduce(LoadTiles{dvals, rect, tw, th}, n_vis, n_max, counts + 1, tmp, st);
+    const int nb = scan_reduce(LoadTiles{rect, tw, th}, n_vis, n_max, counts + 1, tmp, st);
     launch_finalize_counts(counts, cap, flags, st);
     hipLaunchKernelGGL(k_emit_down, dim3(nb), dim3(kBS), 0, st, dvals, n_vis, nb, tmp.partial,
                        rect, tw, th, tiles_x, cap, ikeys, ivals, ioff);
@@ -449,7 +449,7 @@ __global__ __launch_bounds__(kBS) void k_seg_scatter(
     const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__restrict__ kout,
     uint32_t *__restrict__ vout, const uint32_t *__restrict__ seg,
     const uint32_t *__restrict__ tp, int n_seg, int shift, const uint32_t *__restrict__ hist,
-    uint32_t seg_key_stride)
+    uint32_t seg_key_stride, const uint2 *__restrict__ pay_src, uint2 *__restrict__ pay_dst)
 {
     constexpr int R = 1 << RB;
     constexpr int DPT = R >= kBS ? R / kBS : 1;  // digits owned by each thread
@@ -547,15 +547,19 @@ __global__ __launch_bounds__(kBS) void k_seg_scatter(
         const K kk = s_keys[p];
         const uint32_t d = (uint32_t)(kk >> shift) & mask;
         const uint32_t g = s_base[d] + p - s_toff[d];
-        kout[g] = kk + add;
-        vout[g] = s_vals[p];
+        const uint32_t v = s_vals[p];
+        if (pay_dst)
+            pay_dst[g] = pay_src[v];  // the keys are not needed after this pass
+        else
+            kout[g] = kk + add;
+        vout[g] = v;
     }
 }
 
 template <typename K, int RB>
 static int seg_sort_rb(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t *seg, int n_seg,
-                       uint32_t n_max, int bits, uint32_t stride, const SegSortTemp &tmp,
-                       hipStream_t st)
+                       uint32_t n_max, int bits, uint32_t stride, const uint2 *pay_src,
+                       uint2 *pay_dst, const SegSortTemp &tmp, hipStream_t st)
 {
     constexpr int R = 1 << RB;
     const uint32_t max_tiles =
@@ -571,9 +575,10 @@ static int seg_sort_rb(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t 
         hipLaunchKernelGGL((k_seg_hist<K, RB>), dim3(max_tiles), dim3(kBS), 0, st, ki, seg, tmp.tp,
                            n_seg, shift, tmp.hist);
         scan_u32(tmp.hist, tmp.hist_len, max_tiles * (uint32_t)R, tmp.hist, nullptr, tmp.scan, st);
-        const uint32_t add = shift + RB >= bits ? stride : 0u;
+        const bool last = shift + RB >= bits;
         hipLaunchKernelGGL((k_seg_scatter<K, RB>), dim3(max_tiles), dim3(kBS), 0, st, ki, vi, ko,
-                           vo, seg, tmp.tp, n_seg, shift, tmp.hist, add);
+                           vo, seg, tmp.tp, n_seg, shift, tmp.hist, last ? stride : 0u,
+                           last ? pay_src : nullptr, last ? pay_dst : nullptr);
         cur ^= 1;
     }
     return cur;
@@ -586,30 +591,24 @@ uint64_t seg_sort_hist_entries(uint32_t n_max, int n_seg)
 
 int seg_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *seg,
                  int n_seg, uint32_t n_max, int bits, uint32_t seg_key_stride,
-                 const SegSortTemp &tmp, hipStream_t st)
+                 const SegSortTemp &tmp, hipStream_t st, const uint2 *pay_src, uint2 *pay_dst)
 {
     if (bits <= 0) return 0;
     // as many 8-bit passes as needed, with the bits spread evenly over them
     // (narrower digits: fewer ballots per rank, longer runs per write)
     const int passes = (bits + 7) / 8;
     const int rb = (bits + passes - 1) / passes;
+#define GS_SEG(RB_)                                                                               \
+    return seg_sort_rb<uint32_t, RB_>(k0, v0, k1, v1, seg, n_seg, n_max, bits, seg_key_stride,   \
+                                      pay_src, pay_dst, tmp, st);
     switch (rb) {
-    case 1: case 2: case 3: case 4:
-        return seg_sort_rb<uint32_t, 4>(k0, v0, k1, v1, seg, n_seg, n_max, bits, seg_key_stride,
-                                        tmp, st);
-    case 5:
-        return seg_sort_rb<uint32_t, 5>(k0, v0, k1, v1, seg, n_seg, n_max, bits, seg_key_stride,
-                                        tmp, st);
-    case 6:
-        return seg_sort_rb<uint32_t, 6>(k0, v0, k1, v1, seg, n_seg, n_max, bits, seg_key_stride,
-                                        tmp, st);
-    case 7:
-        return seg_sort_rb<uint32_t, 7>(k0, v0, k1, v1, seg, n_seg, n_max, bits, seg_key_stride,
-                                        tmp, st);
-    default:
-        return seg_sort_rb<uint32_t, 8>(k0, v0, k1, v1, seg, n_seg, n_max, bits, seg_key_stride,
-                                        tmp, st);
+    case 1: case 2: case 3: case 4: GS_SEG(4)
+    case 5: GS_SEG(5)
+    case 6: GS_SEG(6)
+    case 7: GS_SEG(7)
+    default: GS_SEG(8)
     }
+#undef GS_SEG
 }
 
 }  // namespace gs

@@ -79,8 +79,9 @@ void scan_u32(const uint32_t *in, const uint32_t *n_dev, uint32_t n_max, uint32_
 void compact_visible(const uint64_t *vis, uint32_t n_words, const uint32_t *cam_slot, int n_cams,
                      const uint32_t *zbits, uint32_t *keys, uint32_t *vals, uint32_t *n_vis_out,
                      uint32_t *seg_start, const ScanTemp &tmp, hipStream_t st);
-// Tile instances of the depth-sorted records, keyed by the tile index inside
-// the camera: counts[1] = instances, counts[2] = min(instances, cap), flags
+// Tile instances of the depth-sorted records (slots dvals, pixel boxes rect,
+// both in sorted order), keyed by the tile index inside the camera:
+// counts[1] = instances, counts[2] = min(instances, cap), flags
 // updated; entries past cap dropped; ioff[i] = first instance of record i;
 // inst_start[c] (c <= n_cams) = first instance of camera c.
 void emit_instances(const uint32_t *dvals, const uint32_t *n_vis, uint32_t n_max,
@@ -91,11 +92,13 @@ void emit_instances(const uint32_t *dvals, const uint32_t *n_vis, uint32_t n_max
 // Stable sort of u32 keys by their low `bits` bits inside the segments
 // [seg[c], seg[c+1]) (on the device; seg[0] = 0, n_seg <= 4096, the segments
 // tile [0, seg[n_seg]) and seg[n_seg] <= n_max). The last pass adds
-// c * seg_key_stride to the keys of segment c. Returns 0 if the result is in
-// (k0, v0), 1 if in (k1, v1).
+// c * seg_key_stride to the keys of segment c; with pay_dst set it writes
+// pay_dst[i] = pay_src[value i] in sorted order instead of the keys. Returns
+// 0 if the result is in (k0, v0), 1 if in (k1, v1).
 int seg_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *seg,
                  int n_seg, uint32_t n_max, int bits, uint32_t seg_key_stride,
-                 const SegSortTemp &tmp, hipStream_t st);
+                 const SegSortTemp &tmp, hipStream_t st, const uint2 *pay_src = nullptr,
+                 uint2 *pay_dst = nullptr);
 uint64_t seg_sort_hist_entries(uint32_t n_max, int n_seg);
 
 void launch_finalize_counts(uint32_t *counts, uint32_t cap, RenderFlags *flags, hipStream_t st);

@@ -103,7 +103,7 @@ struct Plan {
 // Buffers of one chunk pipeline.
 struct Lane {
     DevBuf<float4> recA, recB, recC;
-    DevBuf<uint2> rect;
+    DevBuf<uint2> rect, srect;  // pixel boxes by slot, and in depth order
     DevBuf<uint32_t> zbits;
     DevBuf<uint64_t> vis;
     DevBuf<uint32_t> dkeys[2], dvals[2];
@@ -375,6 +375,7 @@ bool ensure_workspace(gs_ctx *ctx, const Plan &P, int n_lanes)
         moved |= L.recB.reserve(slots);
         moved |= L.recC.reserve(slots);
         moved |= L.rect.reserve(slots);
+        moved |= L.srect.reserve(slots);
         moved |= L.zbits.reserve(slots);
         moved |= L.vis.reserve(slots / 64);
         for (int i = 0; i < 2; ++i) {
@@ -485,12 +486,13 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
         // depth sort inside each camera's segment: key = z bits (z > 0)
         t0 = T.begin();
         const int r = seg_sort_u32(L.dkeys[0].p, L.dvals[0].p, L.dkeys[1].p, L.dvals[1].p,
-                                   L.vis_start.p, c.count, (uint32_t)c.slots, 31, 0u, sort, s);
+                                   L.vis_start.p, c.count, (uint32_t)c.slots, 31, 0u, sort, s,
+                                   L.rect.p, L.srect.p);
         T.end(GS_STAGE_DEPTH_SORT, t0);
         // tile instances in (camera, depth, index) order, keyed by tile
         t0 = T.begin();
         emit_instances(L.dvals[r].p, L.counts.p + 0, (uint32_t)c.slots, L.vis_start.p, c.count,
-                       L.rect.p, ch.tw, ch.th, P.tiles_x, cap, L.ikeys[0].p, L.ivals[0].p,
+                       L.srect.p, ch.tw, ch.th, P.tiles_x, cap, L.ikeys[0].p, L.ivals[0].p,
                        L.ioff.p, L.inst_start.p, L.counts.p, L.flags.p, scan, s);
         T.end(GS_STAGE_EMIT, t0);
         // stable sort by tile inside each camera keeps the depth order in
