@@ -450,3 +450,24 @@ def test_motion_blur_single_gaussian_sideways_closed_form():
     assert np.all(depth[safe & (mean[..., 4] == 0)] == 0)
     # the blur is visible: the covered extent along x exceeds one sub-frame's
     assert (mean[..., 4] > 0).sum() > (imgs[0][..., 4] > 0).sum() + 10
+
+
+# ---------------------------------------------------------------- golden ----
+
+def test_oracle_matches_stored_workload0_values():
+    """The oracle still gives the values stored by
+    tests/golden/make_workload0_oracle.py (regression pin of its arithmetic;
+    the file is regenerated only with a change justified by the paper)."""
+    import os
+    import scenegen
+    path = os.path.join(os.path.dirname(__file__), "golden", "workload0_oracle.txt")
+    rows = [list(map(float, l.split())) for l in open(path) if not l.startswith("#")]
+    sc = scenegen.make_scene(0)
+    cams = scenegen.make_cameras(0)
+    ref = oracle.render(sc, cams["poses"][0], cams["intrinsics"][0], 64, 48)
+    assert len(rows) > 50 and sum(r[6] > 0 for r in rows) > 30
+    for i, j, r, g, b, d, a in rows:
+        i, j = int(i), int(j)
+        np.testing.assert_allclose(ref.rgb[j, i], [r, g, b], rtol=1e-12, atol=1e-15)
+        assert ref.depth[j, i] == pytest.approx(d, rel=1e-12, abs=1e-15)
+        assert ref.alpha[j, i] == pytest.approx(a, rel=1e-12, abs=1e-15)
