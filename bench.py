@@ -37,6 +37,9 @@ HBM_PEAK = 8.0e12                      # B/s
 # loop: 8 for alpha (offset, factor, square-sum), exp at quarter rate (4),
 # 3 for clamp/scale/test, 8 for the transmittance and the 4 accumulators.
 SLOTS_PER_PAIR = 23
+# VALU issue slots of every lane-pair the built raster walk issues: 17
+# full-rate instructions plus v_exp_f32 at quarter rate.
+ISSUED_SLOTS = 21
 
 
 def log(msg):
@@ -323,10 +326,16 @@ def main():
                     "pairs_per_step": pairs, "evaluated_pairs_per_step": evals,
                     "eval_over_contrib": evals / max(pairs, 1),
                     "issued_lanes_per_step": issued, "issued_over_contrib": issued / max(pairs, 1),
+                    # the same roofline over every lane-pair the walk issues
+                    # (18 VALU instructions, v_exp_f32 at quarter rate: 21
+                    # slots): how busy the VALUs are, waste included
+                    "issued_frac": (issued / max(stage_n["raster"] / eager_steps, 1)) * ISSUED_SLOTS
+                                   / (raster_launch_ms * 1e-3) / VALU_PEAK,
                     "slots_per_pair": SLOTS_PER_PAIR, "dominant_stage": dom,
                     "visible_pairs_per_step": sc["visible"], "instances_per_step": sc["instances"]}
         log(f"raster: {raster_launch_ms:.3f} ms/launch, pairs {pairs:.3e}, evaluated {evals:.3e}, "
-            f"issued lanes {issued:.3e}, frac {roofline['frac']:.3f}")
+            f"issued lanes {issued:.3e}, frac {roofline['frac']:.3f}, "
+            f"issued frac {roofline['issued_frac']:.3f}")
         # plain form: per-camera kernel sequence
         if args.plain_steps > 0:
             def step_plain():

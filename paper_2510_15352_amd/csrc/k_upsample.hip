@@ -59,17 +59,39 @@ __global__ void k_up_input(const float *__restrict__ rgb, const float *__restric
     reinterpret_cast<float4 *>(x0f)[p] = make_float4(v[0], v[1], v[2], v[3]);
 }
 
+// Source rows / columns and weight of bilinear 4x upsampling (half-pixel
+// centres, clamped at the border) for full-resolution index t.
+__device__ __forceinline__ void bilinear_src(int t, int n_in, int &i0, int &i1, float &f)
+{
+    float s = ((float)t + 0.5f) * 0.25f - 0.5f;
+    s = fmaxf(s, 0.0f);
+    i0 = min((int)s, n_in - 1);
+    i1 = min(i0 + 1, n_in - 1);
+    f = s - (float)i0;
+}
+
 // ------------------------------------------------------------ conv (MFMA) --
-enum { EPI_RELU_BF16 = 0, EPI_F32 = 1, EPI_MASK_BF16 = 2 };
+enum { EPI_RELU_BF16 = 0, EPI_F32 = 1, EPI_MASK_BF16 = 2, EPI_HEAD = 3 };
+
+// Outputs of the fused head: full-resolution RGB and depth of the images.
+struct HeadOut {
+    const float *x0f;  // low-res input (r, g, b, depth / 10) for the bilinear skip
+    float *rgb, *depth;
+};
 
 // One block = an 8 x 32 output tile of one image, 4 waves; wave w owns rows
 // 2w and 2w+1 (4 M-tiles of 16 pixels) and all COUT/16 N-tiles.
+// EPI_HEAD (inference, 32 -> 64): the epilogue is the network head, 4x
+// pixel shuffle plus the bilinear skip, writing full-resolution RGB and
+// depth directly: lane (lr, lk) holds channels c * 16 + lr (c = 0..3) of its
+// low-res pixels, i.e. the four outputs of sub-pixel (lr / 4, lr % 4).
 template <int CIN, int COUT, int EPI>
 __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ in,
                                                  const uint16_t *__restrict__ wt,
                                                  const float *__restrict__ bias, int H, int W,
                                                  int tiles_x, int tiles_y,
-                                                 const uint16_t *__restrict__ mask, void *out)
+                                                 const uint16_t *__restrict__ mask, void *out,
+                                                 HeadOut head)
 {
     constexpr int NT = COUT / 16;
     __shared__ __attribute__((aligned(16))) uint16_t s_in[kHY * kHX * CIN];
@@ -122,28 +144,75 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ in
             }
         }
     }
-    // epilogue: lane holds channel n*16 + lr of pixels 4*lk + i of each M-tile
+    if constexpr (EPI == EPI_HEAD) {
+        static_assert(COUT == 64, "the head takes 64 channels");
+        const int si = lr >> 2, sj = lr & 3;
+        const int H4 = 4 * H, W4 = 4 * W;
+        const float4 *xi = reinterpret_cast<const float4 *>(head.x0f) + img_base;
+        float bs[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const int y = ty0 + wave * 2 + (m >> 1);
-        if (y >= H) continue;
+        for (int c = 0; c < 4; ++c) bs[c] = bias[c * 16 + lr];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int x = tx0 + (m & 1) * 16 + lk * 4 + i;
-            if (x >= W) continue;
-            const int64_t p = img_base + (int64_t)y * W + x;
+        for (int m = 0; m < 4; ++m) {
+            const int y = ty0 + wave * 2 + (m >> 1);
+            if (y >= H) continue;
+            const int Y = 4 * y + si;
+            int y0, y1;
+            float fy;
+            bilinear_src(Y, H, y0, y1, fy);
 #pragma unroll
-            for (int n = 0; n < NT; ++n) {
-                const int ch = n * 16 + lr;
-                float v = acc[m][n][i];
-                if (EPI == EPI_F32) {
-                    reinterpret_cast<float *>(out)[p * COUT + ch] = v + bias[ch];
-                } else if (EPI == EPI_RELU_BF16) {
-                    v = fmaxf(v + bias[ch], 0.0f);
-                    reinterpret_cast<uint16_t *>(out)[p * COUT + ch] = bf16_bits(v);
-                } else {
-                    v = bf16_to_f(mask[p * COUT + ch]) > 0.0f ? v : 0.0f;  // ReLU'(z) = [a > 0]
-                    reinterpret_cast<uint16_t *>(out)[p * COUT + ch] = bf16_bits(v);
+            for (int i = 0; i < 4; ++i) {
+                const int x = tx0 + (m & 1) * 16 + lk * 4 + i;
+                if (x >= W) continue;
+                const int X = 4 * x + sj;
+                int xa, xb;
+                float fx;
+                bilinear_src(X, W, xa, xb, fx);
+                const float4 v00 = xi[y0 * W + xa], v01 = xi[y0 * W + xb];
+                const float4 v10 = xi[y1 * W + xa], v11 = xi[y1 * W + xb];
+                const float s00[4] = {v00.x, v00.y, v00.z, v00.w};
+                const float s01[4] = {v01.x, v01.y, v01.z, v01.w};
+                const float s10[4] = {v10.x, v10.y, v10.z, v10.w};
+                const float s11[4] = {v11.x, v11.y, v11.z, v11.w};
+                float pred[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float yv = acc[m][c][i] + bs[c];
+                    const float top = s00[c] * (1.0f - fx) + s01[c] * fx;
+                    const float bot = s10[c] * (1.0f - fx) + s11[c] * fx;
+                    pred[c] = top * (1.0f - fy) + bot * fy + yv;
+                }
+                const int64_t q = (int64_t)img * H4 * W4 + (int64_t)Y * W4 + X;
+                head.rgb[q * 3 + 0] = pred[0];
+                head.rgb[q * 3 + 1] = pred[1];
+                head.rgb[q * 3 + 2] = pred[2];
+                head.depth[q] = pred[3] * kUpDepthScale;
+            }
+        }
+    } else {
+        // epilogue: lane holds channel n*16 + lr of pixels 4*lk + i of each M-tile
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int y = ty0 + wave * 2 + (m >> 1);
+            if (y >= H) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = tx0 + (m & 1) * 16 + lk * 4 + i;
+                if (x >= W) continue;
+                const int64_t p = img_base + (int64_t)y * W + x;
+#pragma unroll
+                for (int n = 0; n < NT; ++n) {
+                    const int ch = n * 16 + lr;
+                    float v = acc[m][n][i];
+                    if (EPI == EPI_F32) {
+                        reinterpret_cast<float *>(out)[p * COUT + ch] = v + bias[ch];
+                    } else if (EPI == EPI_RELU_BF16) {
+                        v = fmaxf(v + bias[ch], 0.0f);
+                        reinterpret_cast<uint16_t *>(out)[p * COUT + ch] = bf16_bits(v);
+                    } else {
+                        v = bf16_to_f(mask[p * COUT + ch]) > 0.0f ? v : 0.0f;  // ReLU'(z) = [a > 0]
+                        reinterpret_cast<uint16_t *>(out)[p * COUT + ch] = bf16_bits(v);
+                    }
                 }
             }
         }
@@ -262,14 +331,6 @@ __global__ void k_sum_partials(const float *__restrict__ part, int nblk, int len
 // Inference writes rgb / depth; training also reads the target, accumulates
 // the weighted squared error per block and writes dL/dy (BF16, low-res
 // layout, 64 channels).
-__device__ __forceinline__ void bilinear_src(int t, int n_in, int &i0, int &i1, float &f)
-{
-    float s = ((float)t + 0.5f) * 0.25f - 0.5f;
-    s = fmaxf(s, 0.0f);
-    i0 = min((int)s, n_in - 1);
-    i1 = min(i0 + 1, n_in - 1);
-    f = s - (float)i0;
-}
 
 template <bool TRAIN>
 __global__ __launch_bounds__(256) void k_up_head(const float *__restrict__ x0f,
@@ -477,19 +538,21 @@ void launch_up_input(const float *rgb, const float *depth, int64_t npix, float *
 
 void launch_up_conv(int cin, int cout, int epi, const uint16_t *in, const uint16_t *wt,
                     const float *bias, int n, int h, int w, const uint16_t *mask, void *out,
-                    hipStream_t st)
+                    hipStream_t st, const float *x0f, float *rgb, float *depth)
 {
     int tx, ty;
     tiles_of(h, w, tx, ty);
     dim3 grid(n * tx * ty), block(256);
+    const HeadOut head{x0f, rgb, depth};
 #define GS_CONV(CI, CO, E)                                                                     \
     if (cin == CI && cout == CO && epi == E) {                                                 \
         hipLaunchKernelGGL((k_conv3x3<CI, CO, E>), grid, block, 0, st, in, wt, bias, h, w, tx, \
-                           ty, mask, out);                                                     \
+                           ty, mask, out, head);                                               \
         return;                                                                                \
     }
     GS_CONV(32, 32, EPI_RELU_BF16)
     GS_CONV(32, 64, EPI_F32)
+    GS_CONV(32, 64, EPI_HEAD)
     GS_CONV(64, 32, EPI_MASK_BF16)
     GS_CONV(32, 32, EPI_MASK_BF16)
 #undef GS_CONV

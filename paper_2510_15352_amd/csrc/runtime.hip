@@ -842,13 +842,21 @@ void up_alloc(gs_ctx *ctx, int n, int h, int w, bool train)
 }
 
 // x0b / x0f of n images must be filled; writes y4.
-void up_forward(gs_ctx *ctx, int n, int h, int w, hipStream_t st)
+// Network forward. With rgb / depth set (inference) the last layer's
+// epilogue is the head and writes the full-resolution frames; otherwise the
+// last layer writes y4 (FP32) for the training head.
+void up_forward(gs_ctx *ctx, int n, int h, int w, hipStream_t st, float *rgb = nullptr,
+                float *depth = nullptr)
 {
     Upsampler &U = ctx->up;
     launch_up_conv(32, 32, UP_EPI_RELU_BF16, U.x0b.p, U.wf[0].p, U.b[0].p, n, h, w, nullptr, U.a1.p, st);
     launch_up_conv(32, 32, UP_EPI_RELU_BF16, U.a1.p, U.wf[1].p, U.b[1].p, n, h, w, nullptr, U.a2.p, st);
     launch_up_conv(32, 32, UP_EPI_RELU_BF16, U.a2.p, U.wf[2].p, U.b[2].p, n, h, w, nullptr, U.a3.p, st);
-    launch_up_conv(32, 64, UP_EPI_F32, U.a3.p, U.wf[3].p, U.b[3].p, n, h, w, nullptr, U.y4.p, st);
+    if (rgb)
+        launch_up_conv(32, 64, UP_EPI_HEAD, U.a3.p, U.wf[3].p, U.b[3].p, n, h, w, nullptr,
+                       nullptr, st, U.x0f.p, rgb, depth);
+    else
+        launch_up_conv(32, 64, UP_EPI_F32, U.a3.p, U.wf[3].p, U.b[3].p, n, h, w, nullptr, U.y4.p, st);
 }
 
 // dy4 must be filled (training head); writes gw / gb of every layer.
@@ -1556,9 +1564,7 @@ int gs_upsampler_forward(gs_ctx *ctx, int32_t n, int32_t h, int32_t w, const flo
             up_alloc(ctx, m, h, w, false);
             const int64_t lp = (int64_t)h * w, hp = lp * 16;
             launch_up_input(rgb_lo + c0 * lp * 3, depth_lo + c0 * lp, m * lp, U.x0f.p, U.x0b.p, st);
-            up_forward(ctx, m, h, w, st);
-            launch_up_head(false, U.x0f.p, U.y4.p, h, w, m, rgb_out + c0 * hp * 3,
-                           depth_out + c0 * hp, nullptr, nullptr, nullptr, nullptr, st);
+            up_forward(ctx, m, h, w, st, rgb_out + c0 * hp * 3, depth_out + c0 * hp);
         }
         HIP_CHECK(hipGetLastError());
         return GS_OK;
@@ -1668,9 +1674,7 @@ int gs_render_batch_upsampled(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_
             launch_up_input(U.lo_rgb.p + c0 * lp * 3, U.lo_depth.p + c0 * lp, m * lp, U.x0f.p,
                             U.x0b.p, st);
             launch_up_score(U.x0f.p, m, h, w, U.score.p + c0, st);
-            up_forward(ctx, m, h, w, st);
-            launch_up_head(false, U.x0f.p, U.y4.p, h, w, m, rgb + c0 * hp * 3, depth + c0 * hp,
-                           nullptr, nullptr, nullptr, nullptr, st);
+            up_forward(ctx, m, h, w, st, rgb + c0 * hp * 3, depth + c0 * hp);
         }
         if (score_out)
             HIP_CHECK(hipMemcpyAsync(score_out, U.score.p, (size_t)n_cams * 4,

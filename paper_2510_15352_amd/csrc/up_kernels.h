@@ -10,15 +10,18 @@ constexpr float kUpDepthScale = 10.0f;  // network depth channel = depth / 10 m
 constexpr float kUpDepthInv = 0.1f;
 constexpr float kUpDepthWeight = 0.1f;  // loss weight of the depth channel
 
-enum { UP_EPI_RELU_BF16 = 0, UP_EPI_F32 = 1, UP_EPI_MASK_BF16 = 2 };
+enum { UP_EPI_RELU_BF16 = 0, UP_EPI_F32 = 1, UP_EPI_MASK_BF16 = 2, UP_EPI_HEAD = 3 };
 
 int up_conv_blocks(int n, int h, int w);
 int up_head_blocks(int n, int h, int w);
 void launch_up_input(const float *rgb, const float *depth, int64_t npix, float *x0f,
                      uint16_t *x0b, hipStream_t st);
+// epi UP_EPI_HEAD (32 -> 64, inference): the head is fused into the
+// epilogue, writing full-resolution rgb / depth from x0f (out unused).
 void launch_up_conv(int cin, int cout, int epi, const uint16_t *in, const uint16_t *wt,
                     const float *bias, int n, int h, int w, const uint16_t *mask, void *out,
-                    hipStream_t st);
+                    hipStream_t st, const float *x0f = nullptr, float *rgb = nullptr,
+                    float *depth = nullptr);
 void launch_up_wgrad(int cin, int cout, const uint16_t *x, const uint16_t *dy, int n, int h,
                      int w, float *part, float *partb, hipStream_t st);
 void launch_sum_partials(const float *part, int nblk, int len, float *grad, hipStream_t st);
