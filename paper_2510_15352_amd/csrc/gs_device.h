@@ -50,7 +50,11 @@ struct SceneDev {
 };
 
 // One projection work item: Gaussians [g0, g0 + 256) of `scene` seen by the
-// chunk-local cameras [cam0, cam0 + ncam).
+// chunk-local cameras [cam0, cam0 + ncam), ncam <= kProjCams. A block loads
+// its Gaussians once for all of the item's cameras, so the scene is read
+// once per kProjCams cameras.
+constexpr int kProjCams = 64;
+
 struct ProjItem {
     int32_t scene;
     int32_t g0;

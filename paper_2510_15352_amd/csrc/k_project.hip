@@ -96,9 +96,8 @@ __global__ __launch_bounds__(256) void k_project(
     uint64_t *__restrict__ vis)
 {
     constexpr int NC = (DEG + 1) * (DEG + 1);
-    constexpr int kMaxCams = 16;
-    __shared__ CamParams s_cam[kMaxCams];
-    __shared__ uint32_t s_slot[kMaxCams];
+    __shared__ CamParams s_cam[kProjCams];
+    __shared__ uint32_t s_slot[kProjCams];
     const ProjItem it = items[blockIdx.x];
     {
         // the item's camera constants, staged once per block

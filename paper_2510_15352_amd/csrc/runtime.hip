@@ -285,7 +285,7 @@ std::unique_ptr<Plan> make_plan(gs_ctx *ctx, int n_cams, const int32_t *scene_id
 {
     // a subset renders only the listed batch cameras into their own slots
     if (subset) n_cams = (int)subset->size();
-    constexpr int kCamGroup = 16;
+    constexpr int kCamGroup = kProjCams;
     const uint64_t kSlotBudget = uint64_t(1) << 27;
     auto P = std::make_unique<Plan>();
     P->n_cams = n_cams;
