@@ -74,18 +74,32 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
     s.T = inside ? 1.0f : -1.0f;
     s.r = 0.0f; s.g = 0.0f; s.b = 0.0f; s.zw = 0.0f;
     uint32_t n_eval = 0, n_contrib = 0, n_issue = 0;
+    // Thread j stages record j of every batch (B <= NT). The next batch's
+    // records are fetched into registers while the current one is culled
+    // and walked: its slots before the culling, its records after it.
+    static_assert(B <= NT, "one record per thread and batch");
+    const int tid = (int)threadIdx.x;
+    bool pf = rg.x + (uint32_t)tid < rg.y && tid < B;
+    uint32_t pslot = pf ? a.ivals[rg.x + tid] : 0u;
+    float4 pA = make_float4(0.f, 0.f, 0.f, 0.f), pB = pA, pC = pA;
+    if (pf) {
+        pA = a.recA[pslot];
+        pB = a.recB[pslot];
+        pC = a.recC[pslot];
+    }
     for (uint32_t base = rg.x; base < rg.y; base += B) {
         const int cnt_b = (int)min((uint32_t)B, rg.y - base);
         __syncthreads();
         // R0 = (ex, ey, fy, -log2 o), R1 = (r, g, b, z), R2 = (u, v, tau)
-        for (int j = (int)threadIdx.x; j < cnt_b; j += NT) {
-            const uint32_t slot = a.ivals[base + j];
-            const float4 A = a.recA[slot], Bv = a.recB[slot], C = a.recC[slot];
-            sR[j] = make_float4(A.z, A.w, Bv.x, -__builtin_amdgcn_logf(Bv.y));
-            sR[B + j] = make_float4(Bv.z, Bv.w, C.x, C.y);
-            sR[2 * B + j] = make_float4(A.x, A.y, C.z, 0.0f);
+        if (pf) {
+            sR[tid] = make_float4(pA.z, pA.w, pB.x, -__builtin_amdgcn_logf(pB.y));
+            sR[B + tid] = make_float4(pB.z, pB.w, pC.x, pC.y);
+            sR[2 * B + tid] = make_float4(pA.x, pA.y, pC.z, 0.0f);
         }
         __syncthreads();
+        const uint32_t next = base + B;
+        pf = next + (uint32_t)tid < rg.y && tid < B;
+        if (pf) pslot = a.ivals[next + tid];
         int n = 0;
         if (__ballot(s.T > 0.0f) != 0ull) {
             for (int c0 = 0; c0 < cnt_b; c0 += 64) {
@@ -105,6 +119,11 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
                         make_uint4((uint32_t)j * 16u, __float_as_uint(E0), __float_as_uint(F0), 0u);
                 n += __popcll(m);
             }
+        }
+        if (pf) {
+            pA = a.recA[pslot];
+            pB = a.recB[pslot];
+            pC = a.recC[pslot];
         }
         __syncthreads();  // per-wave lists written before they are read
         if (__ballot(s.T > 0.0f) != 0ull) {
@@ -316,7 +335,7 @@ void launch_ranges(const uint32_t *ikeys, const uint32_t *n_dev, uint2 *ranges, 
 #define GS_RASTER_CASES(X) \
     X(16, 16, 64) X(16, 16, 128) X(16, 16, 256) \
     X(32, 8, 64) X(32, 8, 128) X(32, 8, 256) \
-    X(8, 8, 64) X(8, 8, 128) X(16, 8, 64) X(16, 8, 128) \
+    X(8, 8, 64) X(16, 8, 64) X(16, 8, 128) \
     X(32, 16, 64) X(32, 16, 128)
 
 bool raster_supported(int tw, int th, int b)
