@@ -62,7 +62,8 @@ struct ProjItem {
     int32_t ncam;
 };
 
-// Raster-ready record of a visible (camera, Gaussian) pair, 48 bytes:
+// Raster-ready record of a visible (camera, Gaussian) pair, 48 contiguous
+// bytes (the raster gathers it per tile instance):
 //   A = (u, v, e_x, e_y)   with  e = e_x dx + e_y dy
 //   B = (f_y, opacity, r, g)     f = f_y dy
 //   C = (b, z, tau, 0)

@@ -91,8 +91,8 @@ template <int DEG>
 __global__ __launch_bounds__(256) void k_project(
     const ProjItem *__restrict__ items, const SceneDev *__restrict__ scenes,
     const CamParams *__restrict__ cams, const uint32_t *__restrict__ cam_slot,
-    float near, int W, int H, float4 *__restrict__ recA, float4 *__restrict__ recB,
-    float4 *__restrict__ recC, uint2 *__restrict__ rect, uint32_t *__restrict__ zbits,
+    float near, int W, int H, float4 *__restrict__ rec, uint2 *__restrict__ rect,
+    uint32_t *__restrict__ zbits,
     uint64_t *__restrict__ vis)
 {
     constexpr int NC = (DEG + 1) * (DEG + 1);
@@ -139,9 +139,10 @@ __global__ __launch_bounds__(256) void k_project(
             P.B.z = r;
             P.B.w = gg;
             P.C.x = bb;
-            recA[slot] = P.A;
-            recB[slot] = P.B;
-            recC[slot] = P.C;
+            float4 *r3 = rec + (size_t)slot * 3;  // one 48-byte record
+            r3[0] = P.A;
+            r3[1] = P.B;
+            r3[2] = P.C;
             rect[slot] = make_uint2((uint32_t)P.x0 | ((uint32_t)P.x1 << 16),
                                     (uint32_t)P.y0 | ((uint32_t)P.y1 << 16));
             zbits[slot] = __float_as_uint(P.C.y);
@@ -209,16 +210,16 @@ void launch_camera_setup(const float *poses, const float *intr, const int32_t *c
 
 void launch_project(int deg, const ProjItem *items, int n_items, const SceneDev *scenes,
                     const CamParams *cams, const uint32_t *cam_slot, float near, int W, int H,
-                    float4 *recA, float4 *recB, float4 *recC, uint2 *rect, uint32_t *zbits,
+                    float4 *rec, uint2 *rect, uint32_t *zbits,
                     uint64_t *vis, hipStream_t st)
 {
     if (n_items <= 0) return;
     dim3 grid(n_items), block(256);
     switch (deg) {
-    case 0: hipLaunchKernelGGL(k_project<0>, grid, block, 0, st, items, scenes, cams, cam_slot, near, W, H, recA, recB, recC, rect, zbits, vis); break;
-    case 1: hipLaunchKernelGGL(k_project<1>, grid, block, 0, st, items, scenes, cams, cam_slot, near, W, H, recA, recB, recC, rect, zbits, vis); break;
-    case 2: hipLaunchKernelGGL(k_project<2>, grid, block, 0, st, items, scenes, cams, cam_slot, near, W, H, recA, recB, recC, rect, zbits, vis); break;
-    default: hipLaunchKernelGGL(k_project<3>, grid, block, 0, st, items, scenes, cams, cam_slot, near, W, H, recA, recB, recC, rect, zbits, vis); break;
+    case 0: hipLaunchKernelGGL(k_project<0>, grid, block, 0, st, items, scenes, cams, cam_slot, near, W, H, rec, rect, zbits, vis); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, grid, block, 0, st, items, scenes, cams, cam_slot, near, W, H, rec, rect, zbits, vis); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, grid, block, 0, st, items, scenes, cams, cam_slot, near, W, H, rec, rect, zbits, vis); break;
+    default: hipLaunchKernelGGL(k_project<3>, grid, block, 0, st, items, scenes, cams, cam_slot, near, W, H, rec, rect, zbits, vis); break;
     }
 }
 

@@ -83,9 +83,9 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
     uint32_t pslot = pf ? a.ivals[rg.x + tid] : 0u;
     float4 pA = make_float4(0.f, 0.f, 0.f, 0.f), pB = pA, pC = pA;
     if (pf) {
-        pA = a.recA[pslot];
-        pB = a.recB[pslot];
-        pC = a.recC[pslot];
+        pA = a.rec[(size_t)pslot * 3];
+        pB = a.rec[(size_t)pslot * 3 + 1];
+        pC = a.rec[(size_t)pslot * 3 + 2];
     }
     for (uint32_t base = rg.x; base < rg.y; base += B) {
         const int cnt_b = (int)min((uint32_t)B, rg.y - base);
@@ -121,9 +121,9 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
             }
         }
         if (pf) {
-            pA = a.recA[pslot];
-            pB = a.recB[pslot];
-            pC = a.recC[pslot];
+            pA = a.rec[(size_t)pslot * 3];
+            pB = a.rec[(size_t)pslot * 3 + 1];
+            pC = a.rec[(size_t)pslot * 3 + 2];
         }
         __syncthreads();  // per-wave lists written before they are read
         if (__ballot(s.T > 0.0f) != 0ull) {

@@ -449,7 +449,8 @@ __global__ __launch_bounds__(kBS) void k_seg_scatter(
     const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__restrict__ kout,
     uint32_t *__restrict__ vout, const uint32_t *__restrict__ seg,
     const uint32_t *__restrict__ tp, int n_seg, int shift, const uint32_t *__restrict__ hist,
-    uint32_t seg_key_stride, const uint2 *__restrict__ pay_src, uint2 *__restrict__ pay_dst)
+    uint32_t seg_key_stride, const uint2 *__restrict__ pay_src, uint2 *__restrict__ pay_dst,
+    uint32_t pay_stride)
 {
     constexpr int R = 1 << RB;
     constexpr int DPT = R >= kBS ? R / kBS : 1;  // digits owned by each thread
@@ -549,7 +550,7 @@ __global__ __launch_bounds__(kBS) void k_seg_scatter(
         const uint32_t g = s_base[d] + p - s_toff[d];
         const uint32_t v = s_vals[p];
         if (pay_dst)
-            pay_dst[g] = pay_src[v];  // the keys are not needed after this pass
+            pay_dst[g] = pay_src[(size_t)v * pay_stride];  // keys not needed after this pass
         else
             kout[g] = kk + add;
         vout[g] = v;
@@ -559,7 +560,8 @@ __global__ __launch_bounds__(kBS) void k_seg_scatter(
 template <typename K, int RB>
 static int seg_sort_rb(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t *seg, int n_seg,
                        uint32_t n_max, int bits, uint32_t stride, const uint2 *pay_src,
-                       uint2 *pay_dst, const SegSortTemp &tmp, hipStream_t st)
+                       uint2 *pay_dst, uint32_t pay_stride, const SegSortTemp &tmp,
+                       hipStream_t st)
 {
     constexpr int R = 1 << RB;
     const uint32_t max_tiles =
@@ -578,7 +580,7 @@ static int seg_sort_rb(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t 
         const bool last = shift + RB >= bits;
         hipLaunchKernelGGL((k_seg_scatter<K, RB>), dim3(max_tiles), dim3(kBS), 0, st, ki, vi, ko,
                            vo, seg, tmp.tp, n_seg, shift, tmp.hist, last ? stride : 0u,
-                           last ? pay_src : nullptr, last ? pay_dst : nullptr);
+                           last ? pay_src : nullptr, last ? pay_dst : nullptr, pay_stride);
         cur ^= 1;
     }
     return cur;
@@ -591,7 +593,8 @@ uint64_t seg_sort_hist_entries(uint32_t n_max, int n_seg)
 
 int seg_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *seg,
                  int n_seg, uint32_t n_max, int bits, uint32_t seg_key_stride,
-                 const SegSortTemp &tmp, hipStream_t st, const uint2 *pay_src, uint2 *pay_dst)
+                 const SegSortTemp &tmp, hipStream_t st, const uint2 *pay_src, uint2 *pay_dst,
+                 uint32_t pay_stride)
 {
     if (bits <= 0) return 0;
     // as many 8-bit passes as needed, with the bits spread evenly over them
@@ -600,7 +603,7 @@ int seg_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const u
     const int rb = (bits + passes - 1) / passes;
 #define GS_SEG(RB_)                                                                               \
     return seg_sort_rb<uint32_t, RB_>(k0, v0, k1, v1, seg, n_seg, n_max, bits, seg_key_stride,   \
-                                      pay_src, pay_dst, tmp, st);
+                                      pay_src, pay_dst, pay_stride, tmp, st);
     switch (rb) {
     case 1: case 2: case 3: case 4: GS_SEG(4)
     case 5: GS_SEG(5)

@@ -36,7 +36,7 @@ struct SegSortTemp {
 struct RasterArgs {
     const uint2 *ranges;   // [n_cams * tiles_per_cam] (start, end) into ivals
     const uint32_t *ivals; // tile-sorted instance values (record slots)
-    const float4 *recA, *recB, *recC;
+    const float4 *rec;          // 48-byte records by slot: A, B, C
     const int32_t *cam_global;  // chunk-local -> batch camera index
     int tiles_x, tiles_per_cam, W, H;
     float bg_r, bg_g, bg_b;
@@ -66,7 +66,7 @@ void launch_camera_setup(const float *poses, const float *intr, const int32_t *c
                          int n_cams, int W, int H, CamParams *out, hipStream_t st);
 void launch_project(int deg, const ProjItem *items, int n_items, const SceneDev *scenes,
                     const CamParams *cams, const uint32_t *cam_slot, float near, int W, int H,
-                    float4 *recA, float4 *recB, float4 *recC, uint2 *rect, uint32_t *zbits,
+                    float4 *rec, uint2 *rect, uint32_t *zbits,
                     uint64_t *vis, hipStream_t st);
 void launch_debug_project(const SceneDev &sc, const int32_t *perm, const CamParams *cam,
                           float near, int W, int H, float *out, hipStream_t st);
@@ -93,12 +93,13 @@ void emit_instances(const uint32_t *dvals, const uint32_t *n_vis, uint32_t n_max
 // [seg[c], seg[c+1]) (on the device; seg[0] = 0, n_seg <= 4096, the segments
 // tile [0, seg[n_seg]) and seg[n_seg] <= n_max). The last pass adds
 // c * seg_key_stride to the keys of segment c; with pay_dst set it writes
-// pay_dst[i] = pay_src[value i] in sorted order instead of the keys. Returns
+// pay_dst[i] = pay_src[value i * pay_stride] in sorted order instead of the
+// keys. Returns
 // 0 if the result is in (k0, v0), 1 if in (k1, v1).
 int seg_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *seg,
                  int n_seg, uint32_t n_max, int bits, uint32_t seg_key_stride,
                  const SegSortTemp &tmp, hipStream_t st, const uint2 *pay_src = nullptr,
-                 uint2 *pay_dst = nullptr);
+                 uint2 *pay_dst = nullptr, uint32_t pay_stride = 1);
 uint64_t seg_sort_hist_entries(uint32_t n_max, int n_seg);
 
 void launch_finalize_counts(uint32_t *counts, uint32_t cap, RenderFlags *flags, hipStream_t st);

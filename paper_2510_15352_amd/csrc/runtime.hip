@@ -102,7 +102,7 @@ struct Plan {
 
 // Buffers of one chunk pipeline.
 struct Lane {
-    DevBuf<float4> recA, recB, recC;
+    DevBuf<float4> rec;  // 48-byte records by slot (A, B, C)
     DevBuf<uint2> rect, srect;  // pixel boxes by slot, and in depth order
     DevBuf<uint32_t> zbits;
     DevBuf<uint64_t> vis;
@@ -371,9 +371,7 @@ bool ensure_workspace(gs_ctx *ctx, const Plan &P, int n_lanes)
     ctx->inst_cap = std::min<uint64_t>(ctx->inst_cap, kMaxInstCap);
     for (int l = 0; l < n_lanes; ++l) {
         Lane &L = ctx->lanes[l];
-        moved |= L.recA.reserve(slots);
-        moved |= L.recB.reserve(slots);
-        moved |= L.recC.reserve(slots);
+        moved |= L.rec.reserve(slots * 3);
         moved |= L.rect.reserve(slots);
         moved |= L.srect.reserve(slots);
         moved |= L.zbits.reserve(slots);
@@ -475,7 +473,7 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
         for (int d = 0; d < 4; ++d)
             if (c.item_cnt[d])
                 launch_project(d, P.d_items.p + c.item_off[d], c.item_cnt[d], ctx->d_scenes.p, cams,
-                               cam_slot, near, P.W, P.H, L.recA.p, L.recB.p, L.recC.p, L.rect.p,
+                               cam_slot, near, P.W, P.H, L.rec.p, L.rect.p,
                                L.zbits.p, L.vis.p, s);
         T.end(GS_STAGE_PROJECT, t0);
         // visible count, order-preserving compaction, per-camera segments
@@ -513,9 +511,7 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
         RasterArgs a;
         a.ranges = L.ranges.p;
         a.ivals = L.ivals[r2].p;
-        a.recA = L.recA.p;
-        a.recB = L.recB.p;
-        a.recC = L.recC.p;
+        a.rec = L.rec.p;
         a.cam_global = P.d_order.p + c.start;
         a.tiles_x = P.tiles_x;
         a.tiles_per_cam = P.tiles_per_cam;
