@@ -117,7 +117,7 @@ struct Lane {
     DevBuf<uint32_t> scan_partial, sort_hist, sort_tp, sort_len;
 };
 
-constexpr int kLanes = 2;
+constexpr int kLanes = 3;  // chunk pipelines, one stream each
 
 // How the raster stores a frame: as the frame itself, or as sub-frame k of a
 // blended (motion-blurred) frame (mode 1 for the first, 2 for the others).
@@ -181,9 +181,10 @@ struct gs_ctx {
 
     DevFlags *host_flags = nullptr;  // pinned, one per lane
     hipStream_t capture_stream = nullptr;
-    hipStream_t capture_aux = nullptr;  // second stream of a captured render
-    hipStream_t aux_stream = nullptr;   // second stream of an eager render
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // streams of the lanes after the first, for captured and eager renders
+    hipStream_t capture_aux[kLanes - 1] = {};
+    hipStream_t aux_stream[kLanes - 1] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[kLanes - 1] = {};
 
     Upsampler up;
     std::vector<hipEvent_t> events;  // pool for stage timing
@@ -435,12 +436,13 @@ struct StageTimer {
 };
 
 // Enqueue the whole render of a plan on `st` (also used under capture).
-// With two lanes, odd chunks run on `aux`, forked from `st` after the camera
-// setup and joined back at the end; each lane's chunks are serial on its
-// stream, so a lane's buffers are reused only after its previous raster.
+// With several lanes, chunk ci runs on lane ci mod n_lanes: lane 0 on `st`,
+// lane l > 0 on aux[l - 1], forked from `st` after the camera setup and
+// joined back at the end; each lane's chunks are serial on its stream, so a
+// lane's buffers are reused only after its previous raster.
 void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float *intr, float near,
                     const float bg[3], float *rgb, float *depth, float *alpha, hipStream_t st,
-                    hipStream_t aux, int n_lanes, StageTimer *tm = nullptr,
+                    const hipStream_t *aux, int n_lanes, StageTimer *tm = nullptr,
                     bool count_pairs = false, Blend blend = Blend{})
 {
     StageTimer off{ctx, st, false};
@@ -454,7 +456,7 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
     T.end(GS_STAGE_SETUP, t0);
     if (n_lanes > 1) {
         HIP_CHECK(hipEventRecord(ctx->ev_fork, st));
-        HIP_CHECK(hipStreamWaitEvent(aux, ctx->ev_fork, 0));
+        for (int l = 1; l < n_lanes; ++l) HIP_CHECK(hipStreamWaitEvent(aux[l - 1], ctx->ev_fork, 0));
     }
     int persistent_blocks = 0;
     if (ch.persistent)
@@ -462,7 +464,8 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
     for (size_t ci = 0; ci < P.chunks.size(); ++ci) {
         const Chunk &c = P.chunks[ci];
         Lane &L = ctx->lanes[ci % n_lanes];
-        const hipStream_t s = (ci % n_lanes) ? aux : st;
+        const int lane = (int)(ci % (size_t)n_lanes);
+        const hipStream_t s = lane ? aux[lane - 1] : st;
         T.st = s;
         ScanTemp scan{L.scan_partial.p};
         SegSortTemp sort{L.sort_hist.p, L.sort_tp.p, L.sort_len.p, scan};
@@ -530,9 +533,9 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
                       persistent_blocks, count_pairs ? L.flags.p : nullptr, s);
         T.end(GS_STAGE_RASTER, t0);
     }
-    if (n_lanes > 1) {
-        HIP_CHECK(hipEventRecord(ctx->ev_join, aux));
-        HIP_CHECK(hipStreamWaitEvent(st, ctx->ev_join, 0));
+    for (int l = 1; l < n_lanes; ++l) {
+        HIP_CHECK(hipEventRecord(ctx->ev_join[l - 1], aux[l - 1]));
+        HIP_CHECK(hipStreamWaitEvent(st, ctx->ev_join[l - 1], 0));
     }
     HIP_CHECK(hipGetLastError());
 }
@@ -629,7 +632,8 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
     const bool use_graph = batched && o.use_graph;
     // two lanes (overlapped chunk pipelines) for batched renders, except when
     // timing stages (their durations are measured one kernel at a time)
-    const int n_lanes = (batched && !o.timing && o.streams != 1) ? kLanes : 1;
+    const int n_lanes =
+        (batched && !o.timing) ? (o.streams > 0 ? std::min<int>(o.streams, kLanes) : kLanes) : 1;
     sync_scene_table(ctx);
     ctx->last = gs_stats{};
     int regrows = 0;
@@ -952,10 +956,12 @@ int gs_create(int hip_device, gs_ctx **out)
         HIP_CHECK(hipHostMalloc((void **)&ctx->host_flags, kLanes * sizeof(DevFlags),
                                 hipHostMallocDefault));
         HIP_CHECK(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
-        HIP_CHECK(hipStreamCreateWithFlags(&ctx->capture_aux, hipStreamNonBlocking));
-        HIP_CHECK(hipStreamCreateWithFlags(&ctx->aux_stream, hipStreamNonBlocking));
+        for (int l = 0; l < kLanes - 1; ++l) {
+            HIP_CHECK(hipStreamCreateWithFlags(&ctx->capture_aux[l], hipStreamNonBlocking));
+            HIP_CHECK(hipStreamCreateWithFlags(&ctx->aux_stream[l], hipStreamNonBlocking));
+            HIP_CHECK(hipEventCreateWithFlags(&ctx->ev_join[l], hipEventDisableTiming));
+        }
         HIP_CHECK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
-        HIP_CHECK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
         return GS_OK;
     });
     if (rc != GS_OK) {
@@ -974,10 +980,12 @@ int gs_destroy(gs_ctx *ctx)
     clear_graphs(ctx);
     for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
-    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
-    if (ctx->capture_aux) (void)hipStreamDestroy(ctx->capture_aux);
-    if (ctx->aux_stream) (void)hipStreamDestroy(ctx->aux_stream);
+    for (int l = 0; l < kLanes - 1; ++l) {
+        if (ctx->ev_join[l]) (void)hipEventDestroy(ctx->ev_join[l]);
+        if (ctx->capture_aux[l]) (void)hipStreamDestroy(ctx->capture_aux[l]);
+        if (ctx->aux_stream[l]) (void)hipStreamDestroy(ctx->aux_stream[l]);
+    }
     if (ctx->host_flags) (void)hipHostFree(ctx->host_flags);
     delete ctx;
     return GS_OK;

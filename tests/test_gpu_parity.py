@@ -421,7 +421,8 @@ def test_release_while_graph_holds_scene_is_busy(gpu_renderer):
     gpu_renderer.release_scene(sid)
 
 
-def test_two_stream_pipeline_bitwise_equal_eager_and_graph(gpu_renderer, w1):
+@pytest.mark.parametrize("streams", [2, 3])
+def test_multi_stream_pipelines_bitwise_equal_eager_and_graph(gpu_renderer, w1, streams):
     import torch
     sc, sid, cams = w1
     n = 20
@@ -429,13 +430,13 @@ def test_two_stream_pipeline_bitwise_equal_eager_and_graph(gpu_renderer, w1):
     K = torch.as_tensor(cams["intrinsics"][:n]).cuda()
     one = [_np(t) for t in gpu_renderer.render([sid] * n, P, K, 640, 480, chunk_cams=3,
                                                streams=1)]
-    two = [_np(t) for t in gpu_renderer.render([sid] * n, P, K, 640, 480, chunk_cams=3,
-                                               streams=2)]
-    for x, y in zip(one, two):
+    many = [_np(t) for t in gpu_renderer.render([sid] * n, P, K, 640, 480, chunk_cams=3,
+                                                streams=streams)]
+    for x, y in zip(one, many):
         assert np.array_equal(x, y)
     out = gpu_renderer.alloc_outputs(n, 640, 480)
     for rep in range(3):
-        gpu_renderer.render([sid] * n, P, K, 640, 480, out=out, chunk_cams=3, streams=2,
+        gpu_renderer.render([sid] * n, P, K, 640, 480, out=out, chunk_cams=3, streams=streams,
                             use_graph=True)
         torch.cuda.synchronize()
         for x, y in zip(one, out):
