@@ -86,8 +86,8 @@ typedef struct {
     int32_t timing;    /* record HIP events around every stage (eager renders only) */
     int32_t count_pairs; /* also count contributing / evaluated (pixel, Gaussian) pairs
                             with an instrumented raster kernel (slower; for measurement) */
-    int32_t streams;   /* BATCHED: chunk pipelines, each on its own stream (1..3; 0 =
-                          3): the raster of one chunk overlaps the next chunks'
+    int32_t streams;   /* BATCHED: chunk pipelines, each on its own stream (1..4; 0 =
+                          4): the raster of one chunk overlaps the next chunks'
                           projection and sorts (timing renders always use one) */
     int32_t reserved[2];
 } gs_render_opts;

@@ -117,7 +117,7 @@ struct Lane {
     DevBuf<uint32_t> scan_partial, sort_hist, sort_tp, sort_len;
 };
 
-constexpr int kLanes = 3;  // chunk pipelines, one stream each
+constexpr int kLanes = 4;  // chunk pipelines, one stream each
 
 // How the raster stores a frame: as the frame itself, or as sub-frame k of a
 // blended (motion-blurred) frame (mode 1 for the first, 2 for the others).

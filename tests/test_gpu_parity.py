@@ -421,7 +421,7 @@ def test_release_while_graph_holds_scene_is_busy(gpu_renderer):
     gpu_renderer.release_scene(sid)
 
 
-@pytest.mark.parametrize("streams", [2, 3])
+@pytest.mark.parametrize("streams", [2, 4])
 def test_multi_stream_pipelines_bitwise_equal_eager_and_graph(gpu_renderer, w1, streams):
     import torch
     sc, sid, cams = w1
