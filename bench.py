@@ -340,6 +340,15 @@ def main():
                                    / (raster_launch_ms * 1e-3) / VALU_PEAK,
                     "slots_per_pair": SLOTS_PER_PAIR, "dominant_stage": dom,
                     "visible_pairs_per_step": sc["visible"], "instances_per_step": sc["instances"]}
+        # measured peaks beside the published ones
+        fma_rate, exp_rate, copy_rate = (r.peak_probe(k) for k in (0, 1, 2))
+        roofline["measured_peak"] = {
+            "fma_lane_ops_per_s": fma_rate, "exp_lane_ops_per_s": exp_rate,
+            "copy_bytes_per_s": copy_rate,
+            "frac": achieved / fma_rate,
+            "issued_frac": roofline["issued_frac"] * VALU_PEAK / fma_rate}
+        log(f"measured peaks: FMA {fma_rate / 1e12:.1f} T lane-ops/s, exp {exp_rate / 1e12:.1f} T, "
+            f"copy {copy_rate / 1e12:.2f} TB/s")
         log(f"raster: {raster_launch_ms:.3f} ms/launch, pairs {pairs:.3e}, evaluated {evals:.3e}, "
             f"issued lanes {issued:.3e}, frac {roofline['frac']:.3f}, "
             f"issued frac {roofline['issued_frac']:.3f}")

@@ -203,6 +203,15 @@ int gs_render_batch_motion_blur(gs_ctx *ctx, int32_t n_cams, const int32_t *scen
                                 float shutter, int32_t n_sub, float *rgb, float *depth,
                                 float *alpha, const gs_render_opts *opts, void *stream);
 
+/* Calibration: the rate this GPU sustains (best of 3 timed runs after a
+ * warm-up), the measured peaks beside the published ones in a roofline.
+ *   kind 0: FP32 FMA lane-operations/s (8 independent chains per lane),
+ *   kind 1: v_exp_f32 lane-operations/s (8 independent chains per lane),
+ *   kind 2: HBM bytes/s of a 1 GiB device copy (bytes read + written).
+ * *rate_out (HOST) receives the rate. Synchronous; allocates and frees its
+ * own buffers (up to 2 GiB for kind 2). */
+int gs_peak_probe(gs_ctx *ctx, int32_t kind, double *rate_out);
+
 /* Counters and choices of the last gs_render_batch of the context. */
 int gs_last_stats(gs_ctx *ctx, gs_stats *out);
 

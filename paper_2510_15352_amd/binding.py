@@ -24,7 +24,7 @@ GS_MODE_PLAIN, GS_MODE_BATCHED = 0, 1
 # every symbol include/gs.h declares
 EXPORTS = ("gs_abi_sizes", "gs_default_opts", "gs_create", "gs_destroy", "gs_last_error", "gs_upload_scene",
            "gs_release_scene", "gs_scene_size", "gs_render_batch", "gs_render_due",
-           "gs_render_batch_motion_blur",
+           "gs_render_batch_motion_blur", "gs_peak_probe",
            "gs_last_stats",
            "gs_debug_project", "gs_autotune", "gs_set_instance_capacity", "gs_clear_graphs",
            "gs_upsampler_num_params", "gs_upsampler_init", "gs_upsampler_set_weights",
@@ -101,6 +101,7 @@ def load():
                                 ctypes.POINTER(RenderOpts), ctypes.POINTER(i32), vp]
     L.gs_render_batch_motion_blur.argtypes = [vp, i32, vp, vp, vp, vp, i32, i32, fp, i32, vp, vp,
                                               vp, ctypes.POINTER(RenderOpts), vp]
+    L.gs_peak_probe.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
     L.gs_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.gs_debug_project.argtypes = [vp, i32, vp, vp, i32, i32, fp, vp]
     L.gs_autotune.argtypes = [vp, i32, vp, vp, vp, i32, i32, vp, vp, ctypes.c_char_p, vp]
@@ -304,6 +305,12 @@ class Renderer:
             rgb.data_ptr(), depth.data_ptr(), al.data_ptr() if al is not None else None,
             ctypes.byref(o), ctypes.byref(nd), _stream_ptr(torch)))
         return nd.value
+
+    def peak_probe(self, kind: int) -> float:
+        """Measured rate: 0 FMA lane-ops/s, 1 v_exp_f32 lane-ops/s, 2 copy bytes/s."""
+        v = ctypes.c_double(0.0)
+        self._check(self.lib.gs_peak_probe(self.ctx, int(kind), ctypes.byref(v)))
+        return v.value
 
     def stats(self) -> dict:
         s = Stats()

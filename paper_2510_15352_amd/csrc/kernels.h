@@ -102,6 +102,11 @@ int seg_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const u
                  uint2 *pay_dst = nullptr, uint32_t pay_stride = 1);
 uint64_t seg_sort_hist_entries(uint32_t n_max, int n_seg);
 
+// Calibration kernels (kind 0: FMA chains, 1: v_exp_f32 chains, 2: copy of
+// n float4 from src to dst); `blocks` blocks of 256 threads.
+void launch_probe(int kind, float *scratch, int64_t n, int iters, const float4 *src, float4 *dst,
+                  int blocks, hipStream_t st);
+
 void launch_finalize_counts(uint32_t *counts, uint32_t cap, RenderFlags *flags, hipStream_t st);
 void launch_zero_u32(uint32_t *p, uint64_t n, hipStream_t st);
 void launch_ranges(const uint32_t *ikeys, const uint32_t *n_dev, uint2 *ranges, uint32_t n_max,

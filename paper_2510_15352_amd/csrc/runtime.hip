@@ -1269,6 +1269,51 @@ int gs_render_batch_motion_blur(gs_ctx *ctx, int32_t n_cams, const int32_t *scen
     });
 }
 
+int gs_peak_probe(gs_ctx *ctx, int32_t kind, double *rate_out)
+{
+    if (!ctx || !rate_out) return GS_ERR_INVALID_ARG;
+    if (kind < 0 || kind > 2) return fail(ctx, GS_ERR_INVALID_ARG, "kind must be 0, 1 or 2");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        hipStream_t st = nullptr;
+        HIP_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIP_CHECK(hipEventCreate(&e0));
+        HIP_CHECK(hipEventCreate(&e1));
+        const int blocks = std::max(ctx->cu_count, 1) * 32;  // 8 waves per SIMD
+        const int iters = 4096;
+        const int64_t n = int64_t(1) << 26;                   // 1 GiB of float4
+        DevBuf<float> scratch;
+        DevBuf<float4> src, dst;
+        scratch.reserve((size_t)blocks * 256);
+        if (kind == 2) {
+            src.reserve((size_t)n);
+            dst.reserve((size_t)n);
+            HIP_CHECK(hipMemsetAsync(src.p, 0, (size_t)n * sizeof(float4), st));
+        }
+        float best = 1e30f;
+        for (int rep = 0; rep < 4; ++rep) {  // the first run warms up
+            HIP_CHECK(hipEventRecord(e0, st));
+            launch_probe(kind, scratch.p, n, iters, src.p, dst.p, kind == 2 ? blocks * 4 : blocks,
+                         st);
+            HIP_CHECK(hipEventRecord(e1, st));
+            HIP_CHECK(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) best = std::min(best, ms);
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)hipStreamDestroy(st);
+        const double sec = (double)best * 1e-3;
+        if (kind == 2)
+            *rate_out = 2.0 * (double)n * sizeof(float4) / sec;  // bytes read + written
+        else
+            *rate_out = (double)blocks * 256.0 * iters * 8.0 / sec;  // lane-ops
+        return GS_OK;
+    });
+}
+
 int gs_last_stats(gs_ctx *ctx, gs_stats *out)
 {
     if (!ctx || !out) return GS_ERR_INVALID_ARG;

@@ -380,6 +380,16 @@ def test_motion_blur_degenerate_cases(gpu_renderer, w1):
             assert bool((x == y).all())
 
 
+def test_peak_probes_are_plausible(gpu_renderer):
+    """Measured FMA, exp and copy rates: positive and within the chip's
+    published limits (39.3 T FP32 lane-ops/s without packing, 8 TB/s)."""
+    fma, ex, cp = (gpu_renderer.peak_probe(k) for k in (0, 1, 2))
+    print(f"FMA {fma / 1e12:.2f} T/s, exp {ex / 1e12:.2f} T/s, copy {cp / 1e12:.2f} TB/s")
+    assert 5e12 < fma < 42e12
+    assert 1e12 < ex <= fma * 1.05
+    assert 1e12 < cp < 8.5e12
+
+
 # ----------------------------------------------------------- error paths --
 
 def test_error_codes(gpu_renderer, w0):
