@@ -479,16 +479,21 @@ __global__ __launch_bounds__(kBS) void k_seg_scatter(
     K key[kSegKPT];
     uint32_t val[kSegKPT], dig[kSegKPT], lrank[kSegKPT];
     uint32_t *cnt = s_cnt[wave];
+    // all of the thread's keys and values first: one memory latency per tile
+#pragma unroll
+    for (int k = 0; k < kSegKPT; ++k) {
+        const uint32_t i = st.start + (uint32_t)(wave * 64 * kSegKPT + k * 64) + lane;
+        key[k] = 0;
+        val[k] = 0;
+        if (i < st.end) {
+            key[k] = kin[i];
+            val[k] = vin[i];
+        }
+    }
 #pragma unroll
     for (int k = 0; k < kSegKPT; ++k) {
         const uint32_t i = st.start + (uint32_t)(wave * 64 * kSegKPT + k * 64) + lane;
         const bool valid = i < st.end;
-        key[k] = 0;
-        val[k] = 0;
-        if (valid) {
-            key[k] = kin[i];
-            val[k] = vin[i];
-        }
         dig[k] = (uint32_t)(key[k] >> shift) & mask;
         uint64_t peers = __ballot(valid);
 #pragma unroll
