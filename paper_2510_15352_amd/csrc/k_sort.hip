@@ -280,13 +280,26 @@ __global__ __launch_bounds__(kBS) void k_emit_down(
     block_range(*n_dev, nb, start, end);
     uint32_t base = partial[blockIdx.x];
     const uint32_t lane = __lane_id();
+    // the next step's slot and box are loaded before this step's work
+    uint32_t nslot = 0;
+    uint2 nrect = make_uint2(0, 0);
+    if (start + threadIdx.x < end) {
+        nslot = dvals[start + threadIdx.x];
+        nrect = rect[start + threadIdx.x];
+    }
     for (uint32_t t0 = start; t0 < end; t0 += kBS) {
         const uint32_t i = t0 + threadIdx.x;
         uint32_t slot = 0, kbase = 0, cnt = 0;
         TileBox tb{0, 0, 1, 1};
+        const uint32_t cslot = nslot;
+        const uint2 crect = nrect;
+        if (i + kBS < end) {
+            nslot = dvals[i + kBS];
+            nrect = rect[i + kBS];
+        }
         if (i < end) {
-            slot = dvals[i];
-            tb = tile_box(rect[i], tw, th);
+            slot = cslot;
+            tb = tile_box(crect, tw, th);
             kbase = (uint32_t)tb.ty0 * (uint32_t)tiles_x + (uint32_t)tb.tx0;
             cnt = (uint32_t)(tb.bw * tb.bh);
         }
@@ -355,7 +368,7 @@ void emit_instances(const uint32_t *dvals, const uint32_t *n_vis, uint32_t n_max
 // digit histograms are laid out [segment][digit][tile of segment], so one
 // plain exclusive scan over them yields every (segment, digit, tile)'s output
 // position, stable inside the segment.
-constexpr int kSegKPT = 8;
+constexpr int kSegKPT = 16;
 constexpr int kSegTile = kBS * kSegKPT;
 
 // tp[c] for c <= n_seg (n_seg <= 4096) and hist_len = tp[n_seg] * R.
