@@ -103,7 +103,15 @@ __global__ __launch_bounds__(kBS) void k_scan_reduce(Load ld, const uint32_t *n_
     uint32_t start, end;
     block_range(count_of(n_dev, n_host), nb, start, end);
     uint32_t s = 0;
-    for (uint32_t i = start + threadIdx.x; i < end; i += kBS) s += ld(i);
+    // eight loads in flight per thread (indices past the end read the last
+    // element, which is then not counted, so no load sits under a branch)
+    for (uint32_t i0 = start + threadIdx.x; i0 < end; i0 += 8u * kBS) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = ld(min(i0 + (uint32_t)u * kBS, end - 1u));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += i0 + (uint32_t)u * kBS < end ? v[u] : 0u;
+    }
     uint32_t t;
     block_excl_scan<kWaves>(s, t, s_wave);
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
@@ -444,10 +452,20 @@ __global__ __launch_bounds__(kBS) void k_seg_hist(const K *__restrict__ keys,
     __shared__ uint32_t h[R];
     SegTile st;
     if (!seg_tile<R>(seg, tp, n_seg, st)) return;
+    // every key of the thread is loaded before the first atomic, so a tile
+    // waits for one memory latency rather than one per key
+    K key[kSegKPT];
+#pragma unroll
+    for (int k = 0; k < kSegKPT; ++k) {
+        const uint32_t i = st.start + (uint32_t)(k * kBS) + threadIdx.x;
+        key[k] = i < st.end ? keys[i] : K(0);
+    }
     for (int d = threadIdx.x; d < R; d += kBS) h[d] = 0;
     __syncthreads();
-    for (uint32_t i = st.start + threadIdx.x; i < st.end; i += kBS)
-        atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (uint32_t)(R - 1)], 1u);
+#pragma unroll
+    for (int k = 0; k < kSegKPT; ++k)
+        if (st.start + (uint32_t)(k * kBS) + threadIdx.x < st.end)
+            atomicAdd(&h[(uint32_t)(key[k] >> shift) & (uint32_t)(R - 1)], 1u);
     __syncthreads();
     for (int d = threadIdx.x; d < R; d += kBS) hist[st.hbase + d * st.nt + st.t] = h[d];
 }
