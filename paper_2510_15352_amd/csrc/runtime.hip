@@ -1422,12 +1422,12 @@ int gs_autotune(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
         hipEvent_t e0, e1;
         HIP_CHECK(hipEventCreate(&e0));
         HIP_CHECK(hipEventCreate(&e1));
-        auto time_choice = [&](const Choice &c) -> float {
+        auto time_choice = [&](const Choice &c, int reps) -> float {
             int rr = render_impl(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb,
                                  depth, nullptr, o, st, &c);
             if (rr) throw GsError(rr, ctx->err);
             float best = 1e30f;
-            for (int rep = 0; rep < 2; ++rep) {
+            for (int rep = 0; rep < reps; ++rep) {
                 HIP_CHECK(hipEventRecord(e0, st));
                 rr = render_impl(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb,
                                  depth, nullptr, o, st, &c);
@@ -1444,18 +1444,21 @@ int gs_autotune(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
         float best_ms = 1e30f;
         std::vector<std::pair<Choice, float>> table;
         for (const Choice &c : cands) {
-            float ms = time_choice(c);
+            float ms = time_choice(c, 2);
             table.push_back({c, ms});
             if (ms < best_ms) {
                 best_ms = ms;
                 best = c;
             }
         }
+        // the chunk sizes differ by a few percent: the best shape and its
+        // chunk variants are timed again over more replays
+        const Choice shape = best;
+        best_ms = 1e30f;
         for (int ck : chunks) {
-            Choice c = best;
+            Choice c = shape;
             c.chunk = ck;
-            if (ck == best.chunk) continue;
-            float ms = time_choice(c);
+            float ms = time_choice(c, 6);
             table.push_back({c, ms});
             if (ms < best_ms) {
                 best_ms = ms;
