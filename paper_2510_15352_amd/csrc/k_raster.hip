@@ -60,19 +60,21 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ ike
 
 // -------------------------------------------------------------- raster --
 // One block per (camera, tile); each wave owns an 8x8 pixel block, one pixel
-// per lane. Per LDS batch of B records, every wave first keeps only the
-// records that can reach its 8x8 rectangle (may_touch, 64 records per
-// ballot, compacted with mbcnt into a per-wave list that also carries the
-// record's block-relative offsets E0, F0), then walks that list front to
-// back. A skipped record has alpha < 1/255 at every pixel of the wave, so the
-// per-pixel result is the same as walking the full tile list. The block
-// stops when a barrier count says every pixel is done.
+// per lane, and walks the tile's list on its own (no block barrier). Per
+// batch of B records, 64 at a time with one record per lane, the wave keeps
+// only the records that can reach its 8x8 rectangle (may_touch), appends
+// them in list order to a wave-private LDS list together with the record's
+// block-relative offsets E0, F0, then walks that list front to back. A
+// skipped record has alpha < 1/255 at every pixel of the wave, so the
+// per-pixel result is the same as walking the full tile list. A wave stops
+// once all of its pixels are done.
 template <int TW, int TH, int B, bool COUNT = false>
-__device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &a, float4 *sR,
-                                            uint4 *sL, RenderFlags *cnt = nullptr)
+__device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &a, float4 *sR0,
+                                            float4 *sR1, float2 *sEF,
+                                            RenderFlags *cnt = nullptr)
 {
     static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are made of 8x8 wave blocks");
-    constexpr int NT = TW * TH;
+    static_assert(B % 64 == 0, "batches are whole sets of 64 records");
     constexpr int SX = TW / 8;
     const int wave = (int)threadIdx.x >> 6;
     const uint32_t lane = __lane_id();
@@ -85,105 +87,98 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
     const float ww = (float)(min(wx0 + 7, a.W - 1) - wx0), wh = (float)(min(wy0 + 7, a.H - 1) - wy0);
     const float cx0 = (float)wx0 + 0.5f, cy0 = (float)wy0 + 0.5f;
     const uint2 rg = a.ranges[(uint32_t)cl * (uint32_t)a.tiles_per_cam + (uint32_t)tile];
-    uint4 *list = sL + wave * B;
+    float4 *L0 = sR0 + wave * B;
+    float4 *L1 = sR1 + wave * B;
+    float2 *LE = sEF + wave * B;
     const uint64_t lt = lanemask_lt();
-    const char *lds = reinterpret_cast<const char *>(sR);
     Pixel s;
     s.T = inside ? 1.0f : -1.0f;
     s.r = 0.0f; s.g = 0.0f; s.b = 0.0f; s.zw = 0.0f;
     uint32_t n_eval = 0, n_contrib = 0, n_issue = 0;
-    // Thread j stages record j of every batch (B <= NT). The next batch's
-    // records are fetched into registers while the current one is culled
-    // and walked: its slots before the culling, its records after it.
-    static_assert(B <= NT, "one record per thread and batch");
-    const int tid = (int)threadIdx.x;
-    bool pf = rg.x + (uint32_t)tid < rg.y && tid < B;
-    uint32_t pslot = pf ? a.ivals[rg.x + tid] : 0u;
+    // Record of the lane in the current set of 64, in registers. The next
+    // set's slot is loaded before the culling and its record after it, so
+    // both are in flight while the wave culls and walks.
+    bool pf = rg.x + lane < rg.y;
+    uint32_t pslot = pf ? a.ivals[rg.x + lane] : 0u;
     float4 pA = make_float4(0.f, 0.f, 0.f, 0.f), pB = pA, pC = pA;
     if (pf) {
         pA = a.rec[(size_t)pslot * 3];
         pB = a.rec[(size_t)pslot * 3 + 1];
         pC = a.rec[(size_t)pslot * 3 + 2];
     }
-    for (uint32_t base = rg.x; base < rg.y; base += B) {
-        const int cnt_b = (int)min((uint32_t)B, rg.y - base);
-        __syncthreads();
-        // R0 = (ex, ey, fy, -log2 o), R1 = (r, g, b, z), R2 = (u, v, tau)
-        if (pf) {
-            sR[tid] = make_float4(pA.z, pA.w, pB.x, -__builtin_amdgcn_logf(pB.y));
-            sR[B + tid] = make_float4(pB.z, pB.w, pC.x, pC.y);
-            sR[2 * B + tid] = make_float4(pA.x, pA.y, pC.z, 0.0f);
-        }
-        __syncthreads();
-        const uint32_t next = base + B;
-        pf = next + (uint32_t)tid < rg.y && tid < B;
-        if (pf) pslot = a.ivals[next + tid];
+    bool live = __ballot(s.T > 0.0f) != 0ull;
+    for (uint32_t base = rg.x; live && base < rg.y; base += B) {
         int n = 0;
-        if (__ballot(s.T > 0.0f) != 0ull) {
-            for (int c0 = 0; c0 < cnt_b; c0 += 64) {
-                const int j = c0 + (int)lane;
-                bool hit = false;
-                float E0 = 0.0f, F0 = 0.0f;
-                if (j < cnt_b) {
-                    const float4 R0 = sR[j], R2 = sR[2 * B + j];
-                    const float Xw = cx0 - R2.x, Yw = cy0 - R2.y;
-                    hit = may_touch(R0.x, R0.y, R0.z, Xw, Yw, ww, wh, R2.z);
-                    E0 = fmaf(R0.x, Xw, R0.y * Yw);
-                    F0 = R0.z * Yw;
-                }
-                const uint64_t m = __ballot(hit);
-                if (hit)
-                    list[n + __popcll(m & lt)] =
-                        make_uint4((uint32_t)j * 16u, __float_as_uint(E0), __float_as_uint(F0), 0u);
-                n += __popcll(m);
-            }
-        }
-        if (pf) {
-            pA = a.rec[(size_t)pslot * 3];
-            pB = a.rec[(size_t)pslot * 3 + 1];
-            pC = a.rec[(size_t)pslot * 3 + 2];
-        }
-        __syncthreads();  // per-wave lists written before they are read
-        if (__ballot(s.T > 0.0f) != 0ull) {
-            // four list entries per step, a wave-level completion test after
-            // each step, then the remainder one by one
-            int k = 0;
-            bool live = true;
-            for (; k + 4 <= n; k += 4) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint4 e = list[k + u];
-                    const float4 R0 = *reinterpret_cast<const float4 *>(lds + e.x);
-                    const float4 R1 = *reinterpret_cast<const float4 *>(lds + B * 16 + e.x);
-                    if (COUNT) {
-                        n_eval += s.T > 0.0f;
-                        ++n_issue;
-                        n_contrib += composite(s, lx, ly, R0, R1, __uint_as_float(e.y),
-                                               __uint_as_float(e.z));
-                    } else {
-                        composite(s, lx, ly, R0, R1, __uint_as_float(e.y), __uint_as_float(e.z));
-                    }
-                }
-                if (__ballot(s.T > 0.0f) == 0ull) {
-                    live = false;
-                    break;
-                }
+        for (int sb = 0; sb < B / 64; ++sb) {
+            const uint32_t j0 = base + (uint32_t)(sb * 64);
+            if (j0 >= rg.y) break;
+            const bool have = pf;
+            const float4 A = pA, Bv = pB, C = pC;
+            const uint32_t nj = j0 + 64u;
+            pf = nj + lane < rg.y;
+            if (pf) pslot = a.ivals[nj + lane];
+            // R0 = (ex, ey, fy, -log2 o), R1 = (r, g, b, z); centre (u, v),
+            // reach tau
+            bool hit = false;
+            float4 R0 = A, R1 = A;
+            float E0 = 0.0f, F0 = 0.0f;
+            if (have) {
+                R0 = make_float4(A.z, A.w, Bv.x, -__builtin_amdgcn_logf(Bv.y));
+                R1 = make_float4(Bv.z, Bv.w, C.x, C.y);
+                const float Xw = cx0 - A.x, Yw = cy0 - A.y;
+                hit = may_touch(R0.x, R0.y, R0.z, Xw, Yw, ww, wh, C.z);
+                E0 = fmaf(R0.x, Xw, R0.y * Yw);
+                F0 = R0.z * Yw;
             }
-            for (; live && k < n; ++k) {
-                const uint4 e = list[k];
-                const float4 R0 = *reinterpret_cast<const float4 *>(lds + e.x);
-                const float4 R1 = *reinterpret_cast<const float4 *>(lds + B * 16 + e.x);
+            const uint64_t m = __ballot(hit);
+            if (hit) {
+                const int p = n + (int)__popcll(m & lt);
+                L0[p] = R0;
+                L1[p] = R1;
+                LE[p] = make_float2(E0, F0);
+            }
+            n += (int)__popcll(m);
+            if (pf) {
+                pA = a.rec[(size_t)pslot * 3];
+                pB = a.rec[(size_t)pslot * 3 + 1];
+                pC = a.rec[(size_t)pslot * 3 + 2];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();  // list entries written before they are read
+        // four list entries per step, a wave-level completion test after
+        // each step, then the remainder one by one
+        int k = 0;
+        for (; k + 4 <= n; k += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float4 R0 = L0[k + u], R1 = L1[k + u];
+                const float2 ef = LE[k + u];
                 if (COUNT) {
                     n_eval += s.T > 0.0f;
                     ++n_issue;
-                    n_contrib += composite(s, lx, ly, R0, R1, __uint_as_float(e.y),
-                                           __uint_as_float(e.z));
+                    n_contrib += composite(s, lx, ly, R0, R1, ef.x, ef.y);
                 } else {
-                    composite(s, lx, ly, R0, R1, __uint_as_float(e.y), __uint_as_float(e.z));
+                    composite(s, lx, ly, R0, R1, ef.x, ef.y);
+                }
+            }
+            if (__ballot(s.T > 0.0f) == 0ull) break;
+        }
+        if (__ballot(s.T > 0.0f) != 0ull) {
+            for (; k < n; ++k) {
+                const float4 R0 = L0[k], R1 = L1[k];
+                const float2 ef = LE[k];
+                if (COUNT) {
+                    n_eval += s.T > 0.0f;
+                    ++n_issue;
+                    n_contrib += composite(s, lx, ly, R0, R1, ef.x, ef.y);
+                } else {
+                    composite(s, lx, ly, R0, R1, ef.x, ef.y);
                 }
             }
         }
-        if (__syncthreads_count(s.T > 0.0f) == 0) break;
+        live = __ballot(s.T > 0.0f) != 0ull;
+        __builtin_amdgcn_wave_barrier();  // list read before the next batch rewrites it
     }
     if (COUNT) {
         // one atomic per wave
@@ -227,10 +222,11 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
     }
 }
 
-// records R0, R1, R2 (B each); one list of B entries per wave
-#define GS_RASTER_SHARED                  \
-    __shared__ float4 sR[3 * B];          \
-    __shared__ uint4 sL[(TW * TH / 64) * B];
+// one list of B entries per wave: R0, R1 and (E0, F0)
+#define GS_RASTER_SHARED                       \
+    __shared__ float4 sR0[(TW * TH / 64) * B]; \
+    __shared__ float4 sR1[(TW * TH / 64) * B]; \
+    __shared__ float2 sEF[(TW * TH / 64) * B];
 
 // Grid forms: one block per (camera, tile) item, item = block index.
 __device__ __forceinline__ uint32_t xcd_item() { return blockIdx.x; }
@@ -243,7 +239,7 @@ void k_raster(RasterArgs a, uint32_t n_items)
     const uint32_t item = xcd_item();
     if (item >= n_items) return;
     raster_tile<TW, TH, B>((int)(item / (uint32_t)a.tiles_per_cam),
-                           (int)(item % (uint32_t)a.tiles_per_cam), a, sR, sL);
+                           (int)(item % (uint32_t)a.tiles_per_cam), a, sR0, sR1, sEF);
 }
 
 // Instrumented grid form: same per-pixel arithmetic, plus counts of
@@ -256,7 +252,7 @@ __global__ __launch_bounds__(TW *TH) void k_raster_count(RasterArgs a, uint32_t 
     const uint32_t item = xcd_item();
     if (item >= n_items) return;
     raster_tile<TW, TH, B, true>((int)(item / (uint32_t)a.tiles_per_cam),
-                                 (int)(item % (uint32_t)a.tiles_per_cam), a, sR, sL, cnt);
+                                 (int)(item % (uint32_t)a.tiles_per_cam), a, sR0, sR1, sEF, cnt);
 }
 
 // Persistent form: a grid sized to the resident capacity pulls
@@ -274,7 +270,7 @@ __global__ __launch_bounds__(TW *TH) void k_raster_persistent(RasterArgs a, uint
         __syncthreads();
         if (item >= n_items) break;
         raster_tile<TW, TH, B>((int)(item / (uint32_t)a.tiles_per_cam),
-                               (int)(item % (uint32_t)a.tiles_per_cam), a, sR, sL);
+                               (int)(item % (uint32_t)a.tiles_per_cam), a, sR0, sR1, sEF);
     }
 }
 
