@@ -161,18 +161,17 @@ __global__ __launch_bounds__(kBS) void k_scan_down(Load ld, const uint32_t *n_de
     }
 }
 
-static int scan_blocks(uint32_t n_max)
+static int scan_blocks(uint32_t n_max, uint32_t per_block = 2048)
 {
-    const uint32_t per_block = 2048;
     uint32_t nb = (n_max + per_block - 1) / per_block;
     return (int)(nb < 1 ? 1 : (nb > kMaxBlocks ? kMaxBlocks : nb));
 }
 
 template <class Load>
 static int scan_reduce(Load ld, const uint32_t *n_dev, uint32_t n_max, uint32_t *total_out,
-                       const ScanTemp &tmp, hipStream_t st)
+                       const ScanTemp &tmp, hipStream_t st, uint32_t per_block = 2048)
 {
-    const int nb = scan_blocks(n_max);
+    const int nb = scan_blocks(n_max, per_block);
     hipLaunchKernelGGL(k_scan_reduce<Load>, dim3(nb), dim3(kBS), 0, st, ld, n_dev, n_max, nb,
                        tmp.partial);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, tmp.partial, nb, total_out);
@@ -269,7 +268,10 @@ void compact_visible(const uint64_t *vis, uint32_t n_words, const uint32_t *cam_
                      uint32_t *seg_start, const ScanTemp &tmp, hipStream_t st)
 {
     if (n_words == 0) return;
-    const int nb = scan_reduce(LoadPopc{vis}, nullptr, n_words, n_vis_out, tmp, st);
+    // one step of kBS words per block where the block limit allows: each
+    // word expands into up to 64 records, so small blocks keep enough of
+    // them in flight
+    const int nb = scan_reduce(LoadPopc{vis}, nullptr, n_words, n_vis_out, tmp, st, kBS);
     hipLaunchKernelGGL(k_compact_down, dim3(nb), dim3(kBS), 0, st, vis, n_words, nb, tmp.partial,
                        cam_slot, n_cams, zbits, keys, vals, seg_start);
     hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, st, n_vis_out, seg_start + n_cams);
