@@ -178,6 +178,10 @@ struct gs_ctx {
     DevBuf<float> blur_poses, blur_offs, blur_asum;
     uint64_t inst_cap = 0;
     int generation = 0;  // bumps whenever a workspace buffer moves
+    // Visibility slots of one camera chunk: the lanes' slot-indexed buffers
+    // (record 48 B, two pixel boxes 16 B, depth key 4 B, two key/value pairs
+    // 16 B) take at most a third of the device memory.
+    uint64_t slot_budget = uint64_t(1) << 27;
 
     DevFlags *host_flags = nullptr;  // pinned, one per lane
     hipStream_t capture_stream = nullptr;
@@ -287,7 +291,7 @@ std::unique_ptr<Plan> make_plan(gs_ctx *ctx, int n_cams, const int32_t *scene_id
     // a subset renders only the listed batch cameras into their own slots
     if (subset) n_cams = (int)subset->size();
     constexpr int kCamGroup = kProjCams;
-    const uint64_t kSlotBudget = uint64_t(1) << 27;
+    const uint64_t kSlotBudget = ctx->slot_budget;
     auto P = std::make_unique<Plan>();
     P->n_cams = n_cams;
     P->W = W;
@@ -953,6 +957,12 @@ int gs_create(int hip_device, gs_ctx **out)
         hipDeviceProp_t prop;
         HIP_CHECK(hipGetDeviceProperties(&prop, hip_device));
         ctx->cu_count = prop.multiProcessorCount;
+        {
+            constexpr uint64_t kSlotBytes = 84;
+            const uint64_t b = (uint64_t)prop.totalGlobalMem / (3 * kLanes * kSlotBytes);
+            ctx->slot_budget = std::min<uint64_t>(std::max<uint64_t>(b, uint64_t(1) << 20),
+                                                  uint64_t(1) << 30);
+        }
         HIP_CHECK(hipHostMalloc((void **)&ctx->host_flags, kLanes * sizeof(DevFlags),
                                 hipHostMallocDefault));
         HIP_CHECK(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
