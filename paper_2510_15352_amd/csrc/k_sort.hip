@@ -283,13 +283,29 @@ __global__ __launch_bounds__(kBS) void k_emit_down(
     const uint32_t *__restrict__ dvals, const uint32_t *__restrict__ n_dev, int nb,
     const uint32_t *__restrict__ partial, const uint2 *__restrict__ rect, int tw, int th,
     int tiles_x, uint32_t cap, uint32_t *__restrict__ ikeys, uint32_t *__restrict__ ivals,
-    uint32_t *__restrict__ ioff)
+    const uint32_t *__restrict__ vis_start, int n_cams, const uint32_t *__restrict__ counts,
+    uint32_t *__restrict__ inst_start)
 {
     __shared__ uint32_t s_wave[kWaves];
+    __shared__ int s_cam;
     uint32_t start, end;
     block_range(*n_dev, nb, start, end);
     uint32_t base = partial[blockIdx.x];
     const uint32_t lane = __lane_id();
+    // first camera whose records start inside this block's range or later
+    // (vis_start is non-decreasing; vis_start[n_cams] = number of records)
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = n_cams;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (vis_start[mid] >= start) hi = mid; else lo = mid + 1;
+        }
+        s_cam = lo;
+    }
+    __syncthreads();
+    int cam = s_cam;
+    uint32_t cam_first = cam < n_cams ? vis_start[cam] : ~0u;  // reloaded only when passed
+    const uint32_t kept = counts[2];
     // the next step's slot and box are loaded before this step's work
     uint32_t nslot = 0;
     uint2 nrect = make_uint2(0, 0);
@@ -315,7 +331,15 @@ __global__ __launch_bounds__(kBS) void k_emit_down(
         }
         uint32_t tot;
         const uint32_t ex = block_excl_scan<kWaves>(cnt, tot, s_wave);
-        if (i < end) ioff[i] = base + ex;
+        // instance segment of every camera whose first record is in this
+        // step: the first instance of that record (cameras without records
+        // share the offset of the next camera's first record)
+        const uint32_t lim = min(t0 + (uint32_t)kBS, end);
+        while (cam_first < lim) {
+            if (i == cam_first) inst_start[cam] = min(base + ex, kept);
+            ++cam;
+            cam_first = cam < n_cams ? vis_start[cam] : ~0u;
+        }
         const uint32_t first = __shfl(ex, 0, 64);
         const uint32_t wave_total = __shfl(ex, 63, 64) + __shfl(cnt, 63, 64) - first;
         const uint32_t lex = ex - first;
@@ -342,33 +366,30 @@ __global__ __launch_bounds__(kBS) void k_emit_down(
     }
 }
 
-// Instance segment of camera c starts at the instance offset of its first
-// record (an empty camera takes the next record's offset, i.e. an empty
-// segment); the last boundary is the number of kept instances.
-__global__ void k_inst_starts(const uint32_t *__restrict__ vis_start, int n_cams,
-                              const uint32_t *__restrict__ ioff,
-                              const uint32_t *__restrict__ counts, uint32_t *__restrict__ inst_start)
+// Instance segment starts, first all set to the number of kept instances
+// (what cameras after the last record keep, and the closing boundary); the
+// emission then writes those of cameras whose first record it meets.
+__global__ void k_inst_starts(int n_cams, const uint32_t *__restrict__ counts,
+                              uint32_t *__restrict__ inst_start)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c > n_cams) return;
-    const uint32_t n_vis = counts[0], kept = counts[2];
-    uint32_t v = kept;
-    if (c < n_cams && vis_start[c] < n_vis) v = min(ioff[vis_start[c]], kept);
-    inst_start[c] = v;
+    inst_start[c] = counts[2];
 }
 
 void emit_instances(const uint32_t *dvals, const uint32_t *n_vis, uint32_t n_max,
                     const uint32_t *vis_start, int n_cams, const uint2 *rect, int tw, int th,
-                    int tiles_x, uint32_t cap, uint32_t *ikeys, uint32_t *ivals, uint32_t *ioff,
+                    int tiles_x, uint32_t cap, uint32_t *ikeys, uint32_t *ivals,
                     uint32_t *inst_start, uint32_t *counts, RenderFlags *flags,
                     const ScanTemp &tmp, hipStream_t st)
 {
     const int nb = scan_reduce(LoadTiles{rect, tw, th}, n_vis, n_max, counts + 1, tmp, st);
     launch_finalize_counts(counts, cap, flags, st);
+    hipLaunchKernelGGL(k_inst_starts, dim3((n_cams + 1 + 255) / 256), dim3(256), 0, st, n_cams,
+                       counts, inst_start);
     hipLaunchKernelGGL(k_emit_down, dim3(nb), dim3(kBS), 0, st, dvals, n_vis, nb, tmp.partial,
-                       rect, tw, th, tiles_x, cap, ikeys, ivals, ioff);
-    hipLaunchKernelGGL(k_inst_starts, dim3((n_cams + 1 + 255) / 256), dim3(256), 0, st, vis_start,
-                       n_cams, ioff, counts, inst_start);
+                       rect, tw, th, tiles_x, cap, ikeys, ivals, vis_start, n_cams, counts,
+                       inst_start);
 }
 
 // ------------------------------------------------------ segmented radix sort --

@@ -82,11 +82,11 @@ void compact_visible(const uint64_t *vis, uint32_t n_words, const uint32_t *cam_
 // Tile instances of the depth-sorted records (slots dvals, pixel boxes rect,
 // both in sorted order), keyed by the tile index inside the camera:
 // counts[1] = instances, counts[2] = min(instances, cap), flags
-// updated; entries past cap dropped; ioff[i] = first instance of record i;
-// inst_start[c] (c <= n_cams) = first instance of camera c.
+// updated; entries past cap dropped; inst_start[c] (c <= n_cams) = first
+// instance of camera c.
 void emit_instances(const uint32_t *dvals, const uint32_t *n_vis, uint32_t n_max,
                     const uint32_t *vis_start, int n_cams, const uint2 *rect, int tw, int th,
-                    int tiles_x, uint32_t cap, uint32_t *ikeys, uint32_t *ivals, uint32_t *ioff,
+                    int tiles_x, uint32_t cap, uint32_t *ikeys, uint32_t *ivals,
                     uint32_t *inst_start, uint32_t *counts, RenderFlags *flags,
                     const ScanTemp &tmp, hipStream_t st);
 // Stable sort of u32 keys by their low `bits` bits inside the segments

@@ -108,7 +108,6 @@ struct Lane {
     DevBuf<uint64_t> vis;
     DevBuf<uint32_t> dkeys[2], dvals[2];
     DevBuf<uint32_t> ikeys[2], ivals[2];
-    DevBuf<uint32_t> ioff;                // first instance of each depth-sorted record
     DevBuf<uint32_t> vis_start, inst_start;  // per-camera segment starts (+ end)
     DevBuf<uint2> ranges;
     DevBuf<uint32_t> counts;  // [0] visible, [1] instances, [2] kept
@@ -387,7 +386,6 @@ bool ensure_workspace(gs_ctx *ctx, const Plan &P, int n_lanes)
             moved |= L.ikeys[i].reserve(ctx->inst_cap);
             moved |= L.ivals[i].reserve(ctx->inst_cap);
         }
-        moved |= L.ioff.reserve(slots);
         moved |= L.vis_start.reserve((uint64_t)P.max_chunk_cams + 1);
         moved |= L.inst_start.reserve((uint64_t)P.max_chunk_cams + 1);
         moved |= L.ranges.reserve((uint64_t)P.max_chunk_cams * P.tiles_per_cam);
@@ -498,7 +496,7 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
         t0 = T.begin();
         emit_instances(L.dvals[r].p, L.counts.p + 0, (uint32_t)c.slots, L.vis_start.p, c.count,
                        L.srect.p, ch.tw, ch.th, P.tiles_x, cap, L.ikeys[0].p, L.ivals[0].p,
-                       L.ioff.p, L.inst_start.p, L.counts.p, L.flags.p, scan, s);
+                       L.inst_start.p, L.counts.p, L.flags.p, scan, s);
         T.end(GS_STAGE_EMIT, t0);
         // stable sort by tile inside each camera keeps the depth order in
         // each tile
