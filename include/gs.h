@@ -79,7 +79,8 @@ typedef struct {
     int32_t mode;      /* GS_MODE_PLAIN or GS_MODE_BATCHED (default BATCHED) */
     int32_t tile_w;    /* raster tile width in pixels; 0 = tuned/default (16) */
     int32_t tile_h;    /* raster tile height; 0 = tuned/default (16) */
-    int32_t lds_batch; /* Gaussians staged in LDS per batch; 0 = tuned/default (256) */
+    int32_t lds_batch; /* records each raster wave fetches, culls and lists in LDS per
+                          batch (64, 128 or 256); 0 = tuned/default (128) */
     int32_t chunk_cams;/* BATCHED: cameras per chunk (1..4096); 0 = tuned/default */
     int32_t persistent;/* BATCHED: raster as a persistent work queue (1), a grid (0), -1 = tuned */
     int32_t use_graph; /* BATCHED: capture the step into a HIP graph and replay it (1) */

@@ -1,6 +1,6 @@
-// Tile binning (instance emission, tile ranges) and the LDS-staged
-// front-to-back rasteriser, as a one-block-per-tile grid or a persistent
-// work queue.
+// Tile ranges and the front-to-back rasteriser (every wave walks its own
+// culled copy of the tile's list), as a one-block-per-tile grid or a
+// persistent work queue; motion-blur pose and finishing kernels.
 #include <algorithm>
 
 #include "gs_device.h"

@@ -1,5 +1,5 @@
 """Parity at the full workload sizes, in the launch configuration bench.py
-times (batched, two streams, HIP-graph replay): every camera of the batch is
+times (batched, four chunk pipelines, HIP-graph replay): every camera of the batch is
 rendered, a seeded sample of cameras is compared with the FP64 oracle
 (max-abs RGB 2e-3, relative depth 1e-3, max-abs alpha 2e-3 with the
 comparator's alternatives), and whole-batch properties are checked on every

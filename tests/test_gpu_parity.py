@@ -273,10 +273,10 @@ def test_empty_cameras_between_visible_ones(gpu_renderer, w0):
 
 
 def test_many_tiles_radix_path_matches_oracle(gpu_renderer, w0):
-    """Above 20480 tiles per camera the tile sort leaves the per-camera LDS
-    counting sort for segmented radix passes plus a ranges kernel: 8x8 tiles
-    on a 1296x1040 image (21060 tiles) against the oracle and against the
-    16x16 tiling, bitwise."""
+    """A camera with 21060 tiles (8x8 tiles on a 1296x1040 image): 15-bit
+    tile keys, so the tile sort runs two 8-bit radix passes instead of the
+    6 + 5 bits of a 640x480 image; checked against the oracle and, bitwise,
+    against the 16x16 tiling."""
     sc, sid, cams = w0
     W, H = 1296, 1040
     intr = np.array([[900.0, 900.0, W / 2, H / 2]] * 2, np.float32)
