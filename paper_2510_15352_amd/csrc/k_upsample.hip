@@ -101,18 +101,34 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ in
     const int t2 = blockIdx.x % (tiles_x * tiles_y);
     const int ty0 = (t2 / tiles_x) * kTY, tx0 = (t2 % tiles_x) * kTX;
     const int64_t img_base = (int64_t)img * H * W;
-    // stage the input tile (zero outside the image) in 16-byte pieces
+    // stage the input tile (zero outside the image) and the weights in
+    // 16-byte pieces: every piece of the thread is loaded before the first
+    // LDS write, so a block waits for one memory latency, not one per piece
     constexpr int PPX = CIN / 8;  // 16-byte pieces per pixel
-    for (int e = tid; e < kHY * kHX * PPX; e += 256) {
+    constexpr int NIN = kHY * kHX * PPX, NIN_T = (NIN + 255) / 256;
+    constexpr int NWT = 9 * COUT * CIN / 8, NWT_T = (NWT + 255) / 256;
+    uint4 vin[NIN_T], vw[NWT_T];
+#pragma unroll
+    for (int k = 0; k < NIN_T; ++k) {
+        const int e = tid + k * 256;
         const int pix = e / PPX, part = e % PPX;
         const int y = ty0 - 1 + pix / kHX, x = tx0 - 1 + pix % kHX;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (y >= 0 && y < H && x >= 0 && x < W)
-            v = reinterpret_cast<const uint4 *>(in + (img_base + (int64_t)y * W + x) * CIN)[part];
-        reinterpret_cast<uint4 *>(s_in)[e] = v;
+        vin[k] = make_uint4(0u, 0u, 0u, 0u);
+        if (e < NIN && y >= 0 && y < H && x >= 0 && x < W)
+            vin[k] = reinterpret_cast<const uint4 *>(in + (img_base + (int64_t)y * W + x) * CIN)[part];
     }
-    for (int e = tid; e < 9 * COUT * CIN / 8; e += 256)
-        reinterpret_cast<uint4 *>(s_w)[e] = reinterpret_cast<const uint4 *>(wt)[e];
+#pragma unroll
+    for (int k = 0; k < NWT_T; ++k) {
+        const int e = tid + k * 256;
+        vw[k] = make_uint4(0u, 0u, 0u, 0u);
+        if (e < NWT) vw[k] = reinterpret_cast<const uint4 *>(wt)[e];
+    }
+#pragma unroll
+    for (int k = 0; k < NIN_T; ++k)
+        if (tid + k * 256 < NIN) reinterpret_cast<uint4 *>(s_in)[tid + k * 256] = vin[k];
+#pragma unroll
+    for (int k = 0; k < NWT_T; ++k)
+        if (tid + k * 256 < NWT) reinterpret_cast<uint4 *>(s_w)[tid + k * 256] = vw[k];
     __syncthreads();
 
     const int wave = tid >> 6, lane = tid & 63;
