@@ -41,21 +41,24 @@ __device__ __forceinline__ uint16_t bf16_bits(float f)
 __device__ __forceinline__ float bf16_to_f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // ------------------------------------------------------------ input prep --
-// x0f[n][y][x][4] = (r, g, b, depth / 10) (FP32, for the skip) and
-// x0b[n][y][x][32] = the same in BF16, channels 4..31 zero.
+// x0f[n][y][x][4] = (r, g, b, depth / 10) (FP32, for the skip) and, when
+// x0b is given (training), x0b[n][y][x][32] = the same in BF16, channels
+// 4..31 zero.
 __global__ void k_up_input(const float *__restrict__ rgb, const float *__restrict__ depth,
                            int64_t npix, float *__restrict__ x0f, uint16_t *__restrict__ x0b)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npix) return;
     const float v[4] = {rgb[p * 3 + 0], rgb[p * 3 + 1], rgb[p * 3 + 2], depth[p] * kUpDepthInv};
-    uint4 *dst = reinterpret_cast<uint4 *>(x0b + p * 32);
-    uint32_t w0 = (uint32_t)bf16_bits(v[0]) | ((uint32_t)bf16_bits(v[1]) << 16);
-    uint32_t w1 = (uint32_t)bf16_bits(v[2]) | ((uint32_t)bf16_bits(v[3]) << 16);
-    dst[0] = make_uint4(w0, w1, 0u, 0u);
-    dst[1] = make_uint4(0u, 0u, 0u, 0u);
-    dst[2] = make_uint4(0u, 0u, 0u, 0u);
-    dst[3] = make_uint4(0u, 0u, 0u, 0u);
+    if (x0b) {
+        uint4 *dst = reinterpret_cast<uint4 *>(x0b + p * 32);
+        uint32_t w0 = (uint32_t)bf16_bits(v[0]) | ((uint32_t)bf16_bits(v[1]) << 16);
+        uint32_t w1 = (uint32_t)bf16_bits(v[2]) | ((uint32_t)bf16_bits(v[3]) << 16);
+        dst[0] = make_uint4(w0, w1, 0u, 0u);
+        dst[1] = make_uint4(0u, 0u, 0u, 0u);
+        dst[2] = make_uint4(0u, 0u, 0u, 0u);
+        dst[3] = make_uint4(0u, 0u, 0u, 0u);
+    }
     reinterpret_cast<float4 *>(x0f)[p] = make_float4(v[0], v[1], v[2], v[3]);
 }
 
@@ -81,11 +84,14 @@ struct HeadOut {
 
 // One block = an 8 x 32 output tile of one image, 4 waves; wave w owns rows
 // 2w and 2w+1 (4 M-tiles of 16 pixels) and all COUT/16 N-tiles.
+// IN4 (first layer at inference): the input tile is built from the FP32
+// four-channel x0f (head.x0f) in LDS, BF16 with channels 4..31 zero, exactly
+// the values the padded BF16 copy would hold.
 // EPI_HEAD (inference, 32 -> 64): the epilogue is the network head, 4x
 // pixel shuffle plus the bilinear skip, writing full-resolution RGB and
 // depth directly: lane (lr, lk) holds channels c * 16 + lr (c = 0..3) of its
 // low-res pixels, i.e. the four outputs of sub-pixel (lr / 4, lr % 4).
-template <int CIN, int COUT, int EPI>
+template <int CIN, int COUT, int EPI, bool IN4 = false>
 __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ in,
                                                  const uint16_t *__restrict__ wt,
                                                  const float *__restrict__ bias, int H, int W,
@@ -107,15 +113,29 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ in
     constexpr int PPX = CIN / 8;  // 16-byte pieces per pixel
     constexpr int NIN = kHY * kHX * PPX, NIN_T = (NIN + 255) / 256;
     constexpr int NWT = 9 * COUT * CIN / 8, NWT_T = (NWT + 255) / 256;
-    uint4 vin[NIN_T], vw[NWT_T];
+    constexpr int NPX_T = (kHY * kHX + 255) / 256;
+    uint4 vin[IN4 ? 1 : NIN_T], vw[NWT_T];
+    float4 vpx[IN4 ? NPX_T : 1];
+    if constexpr (IN4) {
+        static_assert(CIN == 32, "the first layer's input is padded to 32 channels");
 #pragma unroll
-    for (int k = 0; k < NIN_T; ++k) {
-        const int e = tid + k * 256;
-        const int pix = e / PPX, part = e % PPX;
-        const int y = ty0 - 1 + pix / kHX, x = tx0 - 1 + pix % kHX;
-        vin[k] = make_uint4(0u, 0u, 0u, 0u);
-        if (e < NIN && y >= 0 && y < H && x >= 0 && x < W)
-            vin[k] = reinterpret_cast<const uint4 *>(in + (img_base + (int64_t)y * W + x) * CIN)[part];
+        for (int k = 0; k < NPX_T; ++k) {
+            const int pix = tid + k * 256;
+            const int y = ty0 - 1 + pix / kHX, x = tx0 - 1 + pix % kHX;
+            vpx[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (pix < kHY * kHX && y >= 0 && y < H && x >= 0 && x < W)
+                vpx[k] = reinterpret_cast<const float4 *>(head.x0f)[img_base + (int64_t)y * W + x];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NIN_T; ++k) {
+            const int e = tid + k * 256;
+            const int pix = e / PPX, part = e % PPX;
+            const int y = ty0 - 1 + pix / kHX, x = tx0 - 1 + pix % kHX;
+            vin[k] = make_uint4(0u, 0u, 0u, 0u);
+            if (e < NIN && y >= 0 && y < H && x >= 0 && x < W)
+                vin[k] = reinterpret_cast<const uint4 *>(in + (img_base + (int64_t)y * W + x) * CIN)[part];
+        }
     }
 #pragma unroll
     for (int k = 0; k < NWT_T; ++k) {
@@ -123,9 +143,24 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ in
         vw[k] = make_uint4(0u, 0u, 0u, 0u);
         if (e < NWT) vw[k] = reinterpret_cast<const uint4 *>(wt)[e];
     }
+    if constexpr (IN4) {
 #pragma unroll
-    for (int k = 0; k < NIN_T; ++k)
-        if (tid + k * 256 < NIN) reinterpret_cast<uint4 *>(s_in)[tid + k * 256] = vin[k];
+        for (int k = 0; k < NPX_T; ++k) {
+            const int pix = tid + k * 256;
+            if (pix < kHY * kHX) {
+                const float4 v = vpx[k];
+                uint4 *d = reinterpret_cast<uint4 *>(s_in) + pix * PPX;
+                d[0] = make_uint4((uint32_t)bf16_bits(v.x) | ((uint32_t)bf16_bits(v.y) << 16),
+                                  (uint32_t)bf16_bits(v.z) | ((uint32_t)bf16_bits(v.w) << 16), 0u, 0u);
+#pragma unroll
+                for (int q = 1; q < PPX; ++q) d[q] = make_uint4(0u, 0u, 0u, 0u);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NIN_T; ++k)
+            if (tid + k * 256 < NIN) reinterpret_cast<uint4 *>(s_in)[tid + k * 256] = vin[k];
+    }
 #pragma unroll
     for (int k = 0; k < NWT_T; ++k)
         if (tid + k * 256 < NWT) reinterpret_cast<uint4 *>(s_w)[tid + k * 256] = vw[k];
@@ -560,6 +595,11 @@ void launch_up_conv(int cin, int cout, int epi, const uint16_t *in, const uint16
     tiles_of(h, w, tx, ty);
     dim3 grid(n * tx * ty), block(256);
     const HeadOut head{x0f, rgb, depth};
+    if (epi == UP_EPI_RELU_BF16_IN4 && cin == 32 && cout == 32) {
+        hipLaunchKernelGGL((k_conv3x3<32, 32, EPI_RELU_BF16, true>), grid, block, 0, st, in, wt,
+                           bias, h, w, tx, ty, mask, out, head);
+        return;
+    }
 #define GS_CONV(CI, CO, E)                                                                     \
     if (cin == CI && cout == CO && epi == E) {                                                 \
         hipLaunchKernelGGL((k_conv3x3<CI, CO, E>), grid, block, 0, st, in, wt, bias, h, w, tx, \

@@ -851,7 +851,12 @@ void up_forward(gs_ctx *ctx, int n, int h, int w, hipStream_t st, float *rgb = n
                 float *depth = nullptr)
 {
     Upsampler &U = ctx->up;
-    launch_up_conv(32, 32, UP_EPI_RELU_BF16, U.x0b.p, U.wf[0].p, U.b[0].p, n, h, w, nullptr, U.a1.p, st);
+    if (rgb)  // inference: the first layer reads x0f directly
+        launch_up_conv(32, 32, UP_EPI_RELU_BF16_IN4, nullptr, U.wf[0].p, U.b[0].p, n, h, w,
+                       nullptr, U.a1.p, st, U.x0f.p);
+    else
+        launch_up_conv(32, 32, UP_EPI_RELU_BF16, U.x0b.p, U.wf[0].p, U.b[0].p, n, h, w, nullptr,
+                       U.a1.p, st);
     launch_up_conv(32, 32, UP_EPI_RELU_BF16, U.a1.p, U.wf[1].p, U.b[1].p, n, h, w, nullptr, U.a2.p, st);
     launch_up_conv(32, 32, UP_EPI_RELU_BF16, U.a2.p, U.wf[2].p, U.b[2].p, n, h, w, nullptr, U.a3.p, st);
     if (rgb)
@@ -1623,7 +1628,7 @@ int gs_upsampler_forward(gs_ctx *ctx, int32_t n, int32_t h, int32_t w, const flo
             const int m = std::min(kUpChunk, n - c0);
             up_alloc(ctx, m, h, w, false);
             const int64_t lp = (int64_t)h * w, hp = lp * 16;
-            launch_up_input(rgb_lo + c0 * lp * 3, depth_lo + c0 * lp, m * lp, U.x0f.p, U.x0b.p, st);
+            launch_up_input(rgb_lo + c0 * lp * 3, depth_lo + c0 * lp, m * lp, U.x0f.p, nullptr, st);
             up_forward(ctx, m, h, w, st, rgb_out + c0 * hp * 3, depth_out + c0 * hp);
         }
         HIP_CHECK(hipGetLastError());
@@ -1732,7 +1737,7 @@ int gs_render_batch_upsampled(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_
             const int m = std::min(kUpChunk, n_cams - c0);
             up_alloc(ctx, m, h, w, false);
             launch_up_input(U.lo_rgb.p + c0 * lp * 3, U.lo_depth.p + c0 * lp, m * lp, U.x0f.p,
-                            U.x0b.p, st);
+                            nullptr, st);
             launch_up_score(U.x0f.p, m, h, w, U.score.p + c0, st);
             up_forward(ctx, m, h, w, st, rgb + c0 * hp * 3, depth + c0 * hp);
         }

@@ -10,10 +10,14 @@ constexpr float kUpDepthScale = 10.0f;  // network depth channel = depth / 10 m
 constexpr float kUpDepthInv = 0.1f;
 constexpr float kUpDepthWeight = 0.1f;  // loss weight of the depth channel
 
-enum { UP_EPI_RELU_BF16 = 0, UP_EPI_F32 = 1, UP_EPI_MASK_BF16 = 2, UP_EPI_HEAD = 3 };
+// UP_EPI_RELU_BF16_IN4: the first layer at inference, reading its input
+// from x0f (FP32, four channels) instead of the padded BF16 copy.
+enum { UP_EPI_RELU_BF16 = 0, UP_EPI_F32 = 1, UP_EPI_MASK_BF16 = 2, UP_EPI_HEAD = 3,
+       UP_EPI_RELU_BF16_IN4 = 4 };
 
 int up_conv_blocks(int n, int h, int w);
 int up_head_blocks(int n, int h, int w);
+// x0b may be null (inference: the first layer reads x0f).
 void launch_up_input(const float *rgb, const float *depth, int64_t npix, float *x0f,
                      uint16_t *x0b, hipStream_t st);
 // epi UP_EPI_HEAD (32 -> 64, inference): the head is fused into the
