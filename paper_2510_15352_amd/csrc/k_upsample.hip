@@ -102,6 +102,8 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ in
     constexpr int NT = COUT / 16;
     __shared__ __attribute__((aligned(16))) uint16_t s_in[kHY * kHX * CIN];
     __shared__ __attribute__((aligned(16))) uint16_t s_w[9 * COUT * CIN];
+    // the head's bilinear skip reads the FP32 input of the tile and its halo
+    __shared__ float4 s_x0[EPI == EPI_HEAD ? kHY * kHX : 1];
     const int tid = threadIdx.x;
     const int img = blockIdx.x / (tiles_x * tiles_y);
     const int t2 = blockIdx.x % (tiles_x * tiles_y);
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ in
     constexpr int NWT = 9 * COUT * CIN / 8, NWT_T = (NWT + 255) / 256;
     constexpr int NPX_T = (kHY * kHX + 255) / 256;
     uint4 vin[IN4 ? 1 : NIN_T], vw[NWT_T];
-    float4 vpx[IN4 ? NPX_T : 1];
+    float4 vpx[(IN4 || EPI == EPI_HEAD) ? NPX_T : 1];
     if constexpr (IN4) {
         static_assert(CIN == 32, "the first layer's input is padded to 32 channels");
 #pragma unroll
@@ -127,6 +129,16 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ in
                 vpx[k] = reinterpret_cast<const float4 *>(head.x0f)[img_base + (int64_t)y * W + x];
         }
     } else {
+        if constexpr (EPI == EPI_HEAD) {
+#pragma unroll
+            for (int k = 0; k < NPX_T; ++k) {
+                const int pix = tid + k * 256;
+                const int y = ty0 - 1 + pix / kHX, x = tx0 - 1 + pix % kHX;
+                vpx[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (pix < kHY * kHX && y >= 0 && y < H && x >= 0 && x < W)
+                    vpx[k] = reinterpret_cast<const float4 *>(head.x0f)[img_base + (int64_t)y * W + x];
+            }
+        }
 #pragma unroll
         for (int k = 0; k < NIN_T; ++k) {
             const int e = tid + k * 256;
@@ -160,6 +172,11 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ in
 #pragma unroll
         for (int k = 0; k < NIN_T; ++k)
             if (tid + k * 256 < NIN) reinterpret_cast<uint4 *>(s_in)[tid + k * 256] = vin[k];
+        if constexpr (EPI == EPI_HEAD) {
+#pragma unroll
+            for (int k = 0; k < NPX_T; ++k)
+                if (tid + k * 256 < kHY * kHX) s_x0[tid + k * 256] = vpx[k];
+        }
     }
 #pragma unroll
     for (int k = 0; k < NWT_T; ++k)
@@ -199,7 +216,6 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ in
         static_assert(COUT == 64, "the head takes 64 channels");
         const int si = lr >> 2, sj = lr & 3;
         const int H4 = 4 * H, W4 = 4 * W;
-        const float4 *xi = reinterpret_cast<const float4 *>(head.x0f) + img_base;
         float bs[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) bs[c] = bias[c * 16 + lr];
@@ -219,8 +235,11 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ in
                 int xa, xb;
                 float fx;
                 bilinear_src(X, W, xa, xb, fx);
-                const float4 v00 = xi[y0 * W + xa], v01 = xi[y0 * W + xb];
-                const float4 v10 = xi[y1 * W + xa], v11 = xi[y1 * W + xb];
+                // the sources lie within one pixel of (y, x): inside the staged halo
+                const int r0 = (y0 - ty0 + 1) * kHX, r1 = (y1 - ty0 + 1) * kHX;
+                const int ca = xa - tx0 + 1, cb = xb - tx0 + 1;
+                const float4 v00 = s_x0[r0 + ca], v01 = s_x0[r0 + cb];
+                const float4 v10 = s_x0[r1 + ca], v11 = s_x0[r1 + cb];
                 const float s00[4] = {v00.x, v00.y, v00.z, v00.w};
                 const float s01[4] = {v01.x, v01.y, v01.z, v01.w};
                 const float s10[4] = {v10.x, v10.y, v10.z, v10.w};
