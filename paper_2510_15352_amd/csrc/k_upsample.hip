@@ -185,6 +185,11 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ in
 
     const int wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4;
+    // this lane's output-channel biases, loaded while the MFMAs run
+    float bch[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n)
+        bch[n] = (EPI == EPI_F32 || EPI == EPI_RELU_BF16) ? bias[n * 16 + lr] : 0.0f;
     floatx4 acc[4][NT];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -275,9 +280,9 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ in
                     const int ch = n * 16 + lr;
                     float v = acc[m][n][i];
                     if (EPI == EPI_F32) {
-                        reinterpret_cast<float *>(out)[p * COUT + ch] = v + bias[ch];
+                        reinterpret_cast<float *>(out)[p * COUT + ch] = v + bch[n];
                     } else if (EPI == EPI_RELU_BF16) {
-                        v = fmaxf(v + bias[ch], 0.0f);
+                        v = fmaxf(v + bch[n], 0.0f);
                         reinterpret_cast<uint16_t *>(out)[p * COUT + ch] = bf16_bits(v);
                     } else {
                         v = bf16_to_f(mask[p * COUT + ch]) > 0.0f ? v : 0.0f;  // ReLU'(z) = [a > 0]
