@@ -59,25 +59,32 @@ def raster_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed PMC summary, or
-    None when that summary is missing, covers another kernel, or was taken
-    on other raster sources than the ones built now."""
+def measured_traffic(kernel, cams_per_launch):
+    """HBM bytes per launch of `kernel` from the committed PMC summary,
+    scaled from the cameras per launch it was measured at to
+    `cams_per_launch`; None when that summary is missing, has no entry for
+    this kernel, or was taken on other raster sources than the ones built
+    now. Returns (bytes, cameras per launch at measurement)."""
     path = os.path.join(ROOT, TRAFFIC_PROFILE)
     if not os.path.exists(path):
-        return None
-    fields = {}
+        return None, None
+    digest, entries = None, {}
     with open(path) as fh:
         for line in fh:
-            if line.startswith("- ") and ": " in line:
-                k, v = line[2:].split(": ", 1)
-                fields[k.strip()] = v.strip().strip("`")
-    if fields.get("kernel") != kernel or fields.get("sources_sha256") != raster_source_digest():
-        return None
-    try:
-        return float(fields["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+            if line.startswith("- sources_sha256: "):
+                digest = line.split(": ", 1)[1].strip().strip("`")
+            elif line.startswith("- traffic: "):
+                # - traffic: `kernel` bytes_per_launch=B cams_per_launch=C
+                try:
+                    name = line.split("`")[1]
+                    kv = dict(t.split("=") for t in line.split("`")[2].split())
+                    entries[name] = (float(kv["bytes_per_launch"]), float(kv["cams_per_launch"]))
+                except (IndexError, KeyError, ValueError):
+                    continue
+    if digest != raster_source_digest() or kernel not in entries:
+        return None, None
+    b, c = entries[kernel]
+    return b / c * cams_per_launch, c
 
 
 def gen_workload(k):
@@ -175,6 +182,7 @@ def learned_form(args, r, sids, scene_ids, P, K, W, H, n, out, ms_graph, torch):
     fin = np.where(np.isfinite(psnr_e), psnr_e, 200.0)
     log(f"learned: {ms:.2f} ms/step, {n / ms * 1e3:.0f} frames/s, fallback {nf}/{n}, "
         f"PSNR mean {fin.mean():.2f} p5 {np.percentile(fin, 5):.2f} min {fin.min():.2f}")
+    net = network_roofline(r, scene_ids, P, K, W, H, n, torch)
     return {"ms_per_step": ms, "frames_per_s": n / ms * 1e3, "speedup_over_batched": ms_graph / ms,
             "fallback_rate": nf / n, "fallback_threshold": thr,
             "psnr_db": {"mean": float(fin.mean()), "p5": float(np.percentile(fin, 5)),
@@ -187,7 +195,45 @@ def learned_form(args, r, sids, scene_ids, P, K, W, H, n, out, ms_graph, torch):
                                        "heldout_mean_bilinear": float(psnr_bilinear.mean())},
             "train": {"pairs": int(steps * args.train_batch), "batch": args.train_batch,
                       "steps": steps, "seconds": t_train, "loss_first": float(curve[:10].mean()),
-                      "loss_last": float(curve[-10:].mean())}}
+                      "loss_last": float(curve[-10:].mean())},
+            "network": net}
+
+
+# multiply-accumulates per low-resolution pixel of the 4x upsampler: 3x3
+# convolutions 4->32, 32->32, 32->32, 32->64
+UP_MACS_PER_PIXEL = 9 * (4 * 32 + 32 * 32 + 32 * 32 + 32 * 64)
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def network_roofline(r, scene_ids, P, K, W, H, n, torch):
+    """The upsampler network alone on the batch's low-resolution frames:
+    HIP-event time, algorithmic TFLOP/s against the dense BF16 MFMA peak,
+    and its algorithmic HBM traffic (16 B per low-resolution input pixel,
+    16 B per full-resolution output pixel)."""
+    h, w = H // 4, W // 4
+    lo_rgb, lo_depth, _ = r.render(scene_ids, P, K / 4, w, h, alpha=False)
+    r.up_forward(lo_rgb, lo_depth)  # outputs allocated once, then reused by the caching allocator
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        r.up_forward(lo_rgb, lo_depth)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    px = n * h * w
+    tflop = 2.0 * UP_MACS_PER_PIXEL * px / 1e12
+    gbytes = (16 * px + 16 * px * 16) / 1e9
+    tflops = tflop / (ms / 1e3)
+    log(f"network alone: {ms:.2f} ms for {n} frames of {w}x{h}: {tflops:.0f} TFLOP/s "
+        f"({tflops / MFMA_BF16_PEAK_TFLOPS:.3f} of the BF16 MFMA peak), "
+        f"{gbytes / (ms / 1e3):.0f} GB/s algorithmic HBM traffic")
+    return {"ms": ms, "frames": n, "low_res": [w, h], "bound": "mfma",
+            "algorithmic_tflop": tflop, "achieved_tflops": tflops,
+            "peak_tflops": MFMA_BF16_PEAK_TFLOPS, "frac": tflops / MFMA_BF16_PEAK_TFLOPS,
+            "hbm_algorithmic_GB": gbytes, "hbm_GB_per_s": gbytes / (ms / 1e3),
+            "hbm_frac": gbytes / (ms / 1e3) / 8000.0}
 
 
 def main():
@@ -206,6 +252,9 @@ def main():
     ap.add_argument("--only-batched", action="store_true",
                     help="time only the graph-replayed batched form (for profiling)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-upsample form")
+    ap.add_argument("--choice", type=int, nargs=4, default=None, metavar=("TW", "TH", "B", "C"),
+                    help="render with tile TWxTH, LDS batch B, C cameras per chunk (grid "
+                         "raster) instead of the autotuner's choice (for profiling)")
     ap.add_argument("--train-pairs", type=int, default=100_000)
     ap.add_argument("--train-batch", type=int, default=64)
     ap.add_argument("--calib-cams", type=int, default=512)
@@ -250,7 +299,11 @@ def main():
     K = torch.as_tensor(cams["intrinsics"]).cuda()
     out = r.alloc_outputs(n, W, H, alpha=True)
     tuned = None
-    if not args.no_autotune:
+    choice_kw = {}
+    if args.choice:
+        tw, th, b, c = args.choice
+        choice_kw = dict(tile=(tw, th), lds_batch=b, chunk_cams=c, persistent=0)
+    if not args.no_autotune and not args.choice:
         t = time.time()
         out_dir = os.path.join(ROOT, "gpurun_out")
         r.autotune(scene_ids, cams["poses"], cams["intrinsics"], W, H,
@@ -275,7 +328,7 @@ def main():
         if traj is not None:
             P.copy_(traj[sim_step[0] % w.steps])
             sim_step[0] += 1
-        r.render(scene_ids, P, K, W, H, out=out, use_graph=True)
+        r.render(scene_ids, P, K, W, H, out=out, use_graph=True, **choice_kw)
 
     for i in range(args.warmup):
         step_graph()
@@ -296,7 +349,7 @@ def main():
         stage_n = {}
 
         def step_eager():
-            r.render(scene_ids, P, K, W, H, out=out, timing=True)
+            r.render(scene_ids, P, K, W, H, out=out, timing=True, **choice_kw)
             s = r.stats()
             for k, v in s["stage_ms"].items():
                 stage_ms[k] = stage_ms.get(k, 0.0) + v
@@ -314,7 +367,7 @@ def main():
         forms["batched_eager"] = {"ms_per_step": ms_eager, "frames_per_s": n / ms_eager * 1e3,
                                   "stage_ms_per_step": per_step}
         # pair counts (instrumented raster, untimed)
-        r.render(scene_ids, P, K, W, H, out=out, count_pairs=True)
+        r.render(scene_ids, P, K, W, H, out=out, count_pairs=True, **choice_kw)
         sc = r.stats()
         pairs, evals, issued = sc["pairs_contrib"], sc["pairs_evaluated"], sc["pairs_issued"]
         dom = max(per_step, key=per_step.get)
@@ -323,11 +376,15 @@ def main():
         achieved = pairs_per_launch * SLOTS_PER_PAIR / (raster_launch_ms * 1e-3)
         kname = "gs::k_raster<%d, %d, %d>" % (st_graph["tile_w"], st_graph["tile_h"],
                                               st_graph["lds_batch"])
+        launches = stage_n["raster"] / eager_steps
+        traffic, traffic_cams = measured_traffic(kname, n / max(launches, 1))
         roofline = {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12,
                     "peak": VALU_PEAK / 1e12, "unit": "T VALU lane-ops/s",
-                    "frac": achieved / VALU_PEAK, "traffic": measured_traffic(kname),
+                    "frac": achieved / VALU_PEAK, "traffic": traffic,
                     "traffic_unit": "HBM bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, "
-                                    "copy-calibrated)",
+                                    "copy-calibrated; measured at traffic_cams_per_launch "
+                                    "cameras per launch, scaled to this launch's cameras)",
+                    "traffic_cams_per_launch": traffic_cams,
                     "avg_launch_ms": raster_launch_ms,
                     "launches_per_step": stage_n["raster"] / eager_steps,
                     "pairs_per_step": pairs, "evaluated_pairs_per_step": evals,
