@@ -573,23 +573,6 @@ __global__ __launch_bounds__(256) void k_frame_psnr(const float *__restrict__ a,
     }
 }
 
-// Copy full-res frames of the cameras whose flag is set (fallback).
-__global__ void k_copy_flagged(const int32_t *__restrict__ list, int n_list, int64_t npix,
-                               const float *__restrict__ src_rgb, const float *__restrict__ src_d,
-                               float *__restrict__ rgb, float *__restrict__ depth)
-{
-    const int k = blockIdx.y;
-    if (k >= n_list) return;
-    const int64_t cam = list[k];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        rgb[(cam * npix + i) * 3 + 0] = src_rgb[((int64_t)k * npix + i) * 3 + 0];
-        rgb[(cam * npix + i) * 3 + 1] = src_rgb[((int64_t)k * npix + i) * 3 + 1];
-        rgb[(cam * npix + i) * 3 + 2] = src_rgb[((int64_t)k * npix + i) * 3 + 2];
-        depth[cam * npix + i] = src_d[(int64_t)k * npix + i];
-    }
-}
-
 // ---------------------------------------------------------------- launch --
 static void tiles_of(int h, int w, int &tx, int &ty)
 {
@@ -701,14 +684,6 @@ void launch_frame_psnr(const float *a, const float *b, int n, int64_t npix, floa
                        hipStream_t st)
 {
     hipLaunchKernelGGL(k_frame_psnr, dim3(n), dim3(256), 0, st, a, b, npix, out);
-}
-
-void launch_copy_flagged(const int32_t *list, int n_list, int64_t npix, const float *src_rgb,
-                         const float *src_d, float *rgb, float *depth, hipStream_t st)
-{
-    if (n_list <= 0) return;
-    hipLaunchKernelGGL(k_copy_flagged, dim3(256, n_list), dim3(256), 0, st, list, n_list, npix,
-                       src_rgb, src_d, rgb, depth);
 }
 
 }  // namespace gs

@@ -146,9 +146,7 @@ struct Upsampler {
     DevBuf<float> x0f, y4, lpart, wpart, bpart, scalar;
     DevBuf<uint16_t> x0b, a1, a2, a3, dy4, da3, da2, da1;
     // renders used by training and the upsampled form
-    DevBuf<float> lo_rgb, lo_depth, hi_rgb, hi_depth, intr_lo, score, fb_rgb, fb_depth, fb_poses,
-        fb_intr;
-    DevBuf<int32_t> fb_list;
+    DevBuf<float> lo_rgb, lo_depth, hi_rgb, hi_depth, intr_lo, score;
 };
 
 struct GraphEntry {
@@ -1752,31 +1750,12 @@ int gs_render_batch_upsampled(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_
         for (int i = 0; i < n_cams; ++i)
             if (!(sc[i] <= fallback_threshold)) list.push_back(i);
         const int nf = (int)list.size();
+        // the flagged cameras only, rendered straight into their frames of
+        // the batch outputs (over the network's images)
         if (nf > 0) {
-            std::vector<int32_t> sids(nf);
-            for (int k = 0; k < nf; ++k) sids[k] = scene_ids[list[k]];
-            U.fb_list.reserve(nf);
-            U.fb_poses.reserve((size_t)nf * 12);
-            U.fb_intr.reserve((size_t)nf * 4);
-            for (int k0 = 0; k0 < nf; k0 += kUpChunk) {
-                const int m = std::min(kUpChunk, nf - k0);
-                for (int k = 0; k < m; ++k) {
-                    HIP_CHECK(hipMemcpyAsync(U.fb_poses.p + (size_t)k * 12,
-                                             poses + (size_t)list[k0 + k] * 12, 48,
-                                             hipMemcpyDeviceToDevice, st));
-                    HIP_CHECK(hipMemcpyAsync(U.fb_intr.p + (size_t)k * 4,
-                                             intrinsics + (size_t)list[k0 + k] * 4, 16,
-                                             hipMemcpyDeviceToDevice, st));
-                }
-                HIP_CHECK(hipMemcpyAsync(U.fb_list.p, list.data() + k0, (size_t)m * 4,
-                                         hipMemcpyHostToDevice, st));
-                U.fb_rgb.reserve((size_t)m * hp * 3);
-                U.fb_depth.reserve((size_t)m * hp);
-                r = render_impl(ctx, m, sids.data() + k0, U.fb_poses.p, U.fb_intr.p, width, height,
-                                U.fb_rgb.p, U.fb_depth.p, nullptr, o, st, nullptr);
-                if (r) return r;
-                launch_copy_flagged(U.fb_list.p, m, hp, U.fb_rgb.p, U.fb_depth.p, rgb, depth, st);
-            }
+            r = render_impl(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb, depth,
+                            nullptr, o, st, nullptr, &list);
+            if (r) return r;
         }
         HIP_CHECK(hipStreamSynchronize(st));
         ctx->last = lo_stats;

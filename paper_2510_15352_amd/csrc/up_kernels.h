@@ -39,8 +39,6 @@ void launch_adam(float *p, float *m, float *v, const float *g, int n, float lr, 
 void launch_up_score(const float *x0f, int n, int h, int w, float *score, hipStream_t st);
 void launch_frame_psnr(const float *a, const float *b, int n, int64_t npix, float *out,
                        hipStream_t st);
-void launch_copy_flagged(const int32_t *list, int n_list, int64_t npix, const float *src_rgb,
-                         const float *src_d, float *rgb, float *depth, hipStream_t st);
 void launch_quarter_intr(const float *in, int n, float *out, hipStream_t st);
 
 }  // namespace gs

@@ -126,6 +126,16 @@ def test_training_lowers_loss_and_fallback_paths(gpu_renderer):
     ref = U.psnr(rgb.cpu().numpy().astype(np.float64), full[0].cpu().numpy().astype(np.float64))
     np.testing.assert_allclose(ps, ref, atol=1e-3)
     print("psnr", ps)
+    # some cameras fall back: exactly those are the full-resolution render,
+    # written into their own frames; the others keep the upsampled images
+    sc_np = score.cpu().numpy()
+    thr = float(np.sort(sc_np)[3])
+    rgb2, depth2, score2, nf2 = gpu_renderer.render_upsampled(ids, P, K, 640, 480, threshold=thr)
+    flagged = ~(score2.cpu().numpy() <= thr)
+    assert nf2 == int(flagged.sum()) and 0 < nf2 < 8
+    for c in range(8):
+        ref_rgb, ref_d = (full[0][c], full[1][c]) if flagged[c] else (rgb[c], depth[c])
+        assert bool((rgb2[c] == ref_rgb).all()) and bool((depth2[c] == ref_d).all()), c
     gpu_renderer.release_scene(sid)
 
 
