@@ -186,13 +186,14 @@ struct TileBox {
     int tx0, ty0, bw, bh;
 };
 
-__device__ __forceinline__ TileBox tile_box(uint2 r, int tw, int th)
+// Tile sizes are powers of two: lw = log2(tile width), lh = log2(tile height).
+__device__ __forceinline__ TileBox tile_box(uint2 r, int lw, int lh)
 {
     TileBox b;
-    b.tx0 = (int)(r.x & 0xffffu) / tw;
-    b.ty0 = (int)(r.y & 0xffffu) / th;
-    b.bw = (int)(r.x >> 16) / tw - b.tx0 + 1;
-    b.bh = (int)(r.y >> 16) / th - b.ty0 + 1;
+    b.tx0 = (int)((r.x & 0xffffu) >> lw);
+    b.ty0 = (int)((r.y & 0xffffu) >> lh);
+    b.bw = (int)((r.x >> 16) >> lw) - b.tx0 + 1;
+    b.bh = (int)((r.y >> 16) >> lh) - b.ty0 + 1;
     return b;
 }
 

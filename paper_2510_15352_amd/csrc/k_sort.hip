@@ -16,6 +16,8 @@
 //     their tile instances with one lane per output position (load-balanced,
 //     coalesced), finding each position's record by a binary search over the
 //     wave's offsets.
+#include <stdexcept>
+
 #include "gs_device.h"
 #include "kernels.h"
 
@@ -84,10 +86,10 @@ struct LoadPopc {
 // in sorted order by the depth sort's last pass).
 struct LoadTiles {
     const uint2 *rect;
-    int tw, th;
+    int lw, lh;  // log2 of the tile width and height
     __device__ uint32_t operator()(uint32_t i) const
     {
-        const TileBox b = tile_box(rect[i], tw, th);
+        const TileBox b = tile_box(rect[i], lw, lh);
         return (uint32_t)(b.bw * b.bh);
     }
 };
@@ -281,7 +283,7 @@ void compact_visible(const uint64_t *vis, uint32_t n_words, const uint32_t *cam_
 
 __global__ __launch_bounds__(kBS) void k_emit_down(
     const uint32_t *__restrict__ dvals, const uint32_t *__restrict__ n_dev, int nb,
-    const uint32_t *__restrict__ partial, const uint2 *__restrict__ rect, int tw, int th,
+    const uint32_t *__restrict__ partial, const uint2 *__restrict__ rect, int lw, int lh,
     int tiles_x, uint32_t cap, uint32_t *__restrict__ ikeys, uint32_t *__restrict__ ivals,
     const uint32_t *__restrict__ vis_start, int n_cams, const uint32_t *__restrict__ counts,
     uint32_t *__restrict__ inst_start)
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(kBS) void k_emit_down(
         }
         if (i < end) {
             slot = cslot;
-            tb = tile_box(crect, tw, th);
+            tb = tile_box(crect, lw, lh);
             kbase = (uint32_t)tb.ty0 * (uint32_t)tiles_x + (uint32_t)tb.tx0;
             cnt = (uint32_t)(tb.bw * tb.bh);
         }
@@ -383,12 +385,16 @@ void emit_instances(const uint32_t *dvals, const uint32_t *n_vis, uint32_t n_max
                     uint32_t *inst_start, uint32_t *counts, RenderFlags *flags,
                     const ScanTemp &tmp, hipStream_t st)
 {
-    const int nb = scan_reduce(LoadTiles{rect, tw, th}, n_vis, n_max, counts + 1, tmp, st);
+    // tile sizes are powers of two (the raster's tile shapes): shifts, not divisions
+    const int lw = __builtin_ctz((unsigned)tw), lh = __builtin_ctz((unsigned)th);
+    if (tw <= 0 || th <= 0 || (1 << lw) != tw || (1 << lh) != th)
+        throw std::invalid_argument("tile sizes must be powers of two");
+    const int nb = scan_reduce(LoadTiles{rect, lw, lh}, n_vis, n_max, counts + 1, tmp, st);
     launch_finalize_counts(counts, cap, flags, st);
     hipLaunchKernelGGL(k_inst_starts, dim3((n_cams + 1 + 255) / 256), dim3(256), 0, st, n_cams,
                        counts, inst_start);
     hipLaunchKernelGGL(k_emit_down, dim3(nb), dim3(kBS), 0, st, dvals, n_vis, nb, tmp.partial,
-                       rect, tw, th, tiles_x, cap, ikeys, ivals, vis_start, n_cams, counts,
+                       rect, lw, lh, tiles_x, cap, ikeys, ivals, vis_start, n_cams, counts,
                        inst_start);
 }
 
