@@ -81,7 +81,10 @@ typedef struct {
     int32_t tile_h;    /* raster tile height; 0 = tuned/default (16) */
     int32_t lds_batch; /* records each raster wave fetches, culls and lists in LDS per
                           batch (64, 128 or 256); 0 = tuned/default (128) */
-    int32_t chunk_cams;/* BATCHED: cameras per chunk (1..4096); 0 = tuned/default */
+    int32_t chunk_cams;/* BATCHED: cameras per chunk (1..4096); 0 = tuned/default. A
+                          chunk also ends before its cameras' scenes exceed a budget of
+                          Gaussian slots sized from the device memory (84 B per slot in
+                          each of the four pipelines, a third of the memory in all) */
     int32_t persistent;/* BATCHED: raster as a persistent work queue (1), a grid (0), -1 = tuned */
     int32_t use_graph; /* BATCHED: capture the step into a HIP graph and replay it (1) */
     int32_t timing;    /* record HIP events around every stage (eager renders only) */
