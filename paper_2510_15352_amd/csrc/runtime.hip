@@ -166,8 +166,8 @@ struct gs_ctx {
     DevBuf<SceneDev> d_scenes;
     bool scenes_dirty = true;
 
-    // workspace: two lanes, so that one chunk's raster can overlap the next
-    // chunk's projection and sorts on a second stream
+    // workspace: kLanes lanes (one per hardware queue), so that chunks'
+    // rasters overlap other chunks' projection and sorts on other streams
     Lane lanes[kLanes];
     DevBuf<CamParams> cams;
     DevBuf<float> dbg_pose;
@@ -630,8 +630,8 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
         return fail(ctx, GS_ERR_INVALID_ARG, "chunk_cams must be in [1, 4096]");
     const bool batched = o.mode != GS_MODE_PLAIN;
     const bool use_graph = batched && o.use_graph;
-    // two lanes (overlapped chunk pipelines) for batched renders, except when
-    // timing stages (their durations are measured one kernel at a time)
+    // up to kLanes overlapped chunk pipelines for batched renders, except
+    // when timing stages (their durations are measured one kernel at a time)
     const int n_lanes =
         (batched && !o.timing) ? (o.streams > 0 ? std::min<int>(o.streams, kLanes) : kLanes) : 1;
     sync_scene_table(ctx);
