@@ -15,7 +15,8 @@
 //     depth-sorted records, then each wave expands its 64 records into
 //     their tile instances with one lane per output position (load-balanced,
 //     coalesced), finding each position's record by a binary search over the
-//     wave's offsets.
+//     wave's offsets, and writes each camera's instance segment start where
+//     it meets the camera's first record.
 #include <stdexcept>
 
 #include "gs_device.h"
