@@ -13,9 +13,15 @@ out[n, r*y + i, r*x + j, c] = in[n, y, x, c*r*r + i*r + j]. Bilinear 4x with
 half-pixel centres: source coordinate (t + 0.5) / 4 - 0.5, clamped at 0,
 neighbours clamped to the last row/column.
 
+Training step: Adam with bias correction (Kingma & Ba, 2015) on every
+parameter, a cosine learning-rate schedule from lr0 at the first step to
+lr_min at the last, and, for the upsampled render's fallback, a per-frame
+confidence score (mean squared forward difference of the four input
+channels along x and y).
+
 Everything is written from these definitions with numpy loops over the nine
-taps; the tests pin it against torch.nn.functional (float64, CPU) and
-central finite differences.
+taps; the tests pin it against torch.nn.functional and torch.optim.Adam
+(float64, CPU), central finite differences, closed forms and explicit loops.
 """
 from __future__ import annotations
 
@@ -141,3 +147,74 @@ def psnr(pred_rgb, target_rgb):
     b = np.clip(target_rgb, 0.0, 1.0)
     mse = ((a - b) ** 2).reshape(a.shape[0], -1).mean(axis=1)
     return 10.0 * np.log10(1.0 / np.maximum(mse, 1e-12))
+
+
+# ------------------------------------------------------------ training step --
+
+ADAM_B1, ADAM_B2, ADAM_EPS = 0.9, 0.999, 1e-8
+
+
+def adam_step(p, g, m, v, step, lr, b1=ADAM_B1, b2=ADAM_B2, eps=ADAM_EPS):
+    """One Adam update (Kingma & Ba, 2015): step is the 1-based index of this
+    update. m <- b1 m + (1 - b1) g; v <- b2 v + (1 - b2) g^2; with the
+    bias-corrected moments m_hat = m / (1 - b1^step), v_hat = v / (1 -
+    b2^step), p <- p - lr m_hat / (sqrt(v_hat) + eps). Returns new (p, m, v)
+    (float64 arrays)."""
+    p = np.asarray(p, np.float64)
+    g = np.asarray(g, np.float64)
+    m = b1 * np.asarray(m, np.float64) + (1.0 - b1) * g
+    v = b2 * np.asarray(v, np.float64) + (1.0 - b2) * g * g
+    m_hat = m / (1.0 - b1 ** step)
+    v_hat = v / (1.0 - b2 ** step)
+    return p - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
+def cosine_lr(s, steps, lr0, lr_min):
+    """Learning rate of optimisation step s (0-based) of `steps`: half a
+    cosine period from lr0 at s = 0 down to lr_min at s = steps - 1 (lr0
+    throughout when steps == 1)."""
+    if steps <= 1:
+        return float(lr0)
+    return float(lr_min + 0.5 * (lr0 - lr_min) * (1.0 + np.cos(np.pi * s / (steps - 1))))
+
+
+def confidence_score(x0):
+    """Per-frame score of the network input x0 [n, h, w, 4]: the sum over
+    channels of the squared forward differences to the right and downward
+    neighbours (where they exist), divided by the h w pixels of the frame."""
+    x0 = np.asarray(x0, np.float64)
+    n, h, w, _ = x0.shape
+    dx = x0[:, :, 1:, :] - x0[:, :, :-1, :]
+    dy = x0[:, 1:, :, :] - x0[:, :-1, :, :]
+    return ((dx * dx).sum(axis=(1, 2, 3)) + (dy * dy).sum(axis=(1, 2, 3))) / (h * w)
+
+
+def flatten(params):
+    """[(w, b)] per layer -> the parameter vector (per layer: w [cout][3][3][cin], then b)."""
+    return np.concatenate([np.concatenate([w.reshape(-1), b.reshape(-1)]) for (w, b) in params])
+
+
+def unflatten(vec):
+    """Inverse of flatten() for the network's layer shapes."""
+    out, off = [], 0
+    for li in range(4):
+        ci, co = CH[li], CH[li + 1]
+        nw = co * 9 * ci
+        w = np.asarray(vec[off:off + nw], np.float64).reshape(co, 3, 3, ci)
+        off += nw
+        b = np.asarray(vec[off:off + co], np.float64)
+        off += co
+        out.append((w, b))
+    return out
+
+
+def train_step(params, m, v, step, x0, target, lr):
+    """One optimisation step on a batch: forward, loss, backward, then Adam
+    on the parameter vector. params / m / v are parameter vectors; step is
+    the 1-based Adam step. Returns (loss, new params, new m, new v)."""
+    layers = unflatten(params)
+    pred, acts = forward(x0, layers)
+    lval = loss(pred, target)
+    g = flatten(backward(pred, target, acts, layers))
+    p2, m2, v2 = adam_step(params, g, m, v, step, lr)
+    return lval, p2, m2, v2
