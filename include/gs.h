@@ -304,12 +304,45 @@ int gs_upsampler_grads(gs_ctx *ctx, int32_t n, int32_t h, int32_t w, const float
                        const float *depth_lo, const float *rgb_hi, const float *depth_hi,
                        float *loss_out, float *grads_out, void *stream);
 
+/* One optimisation step on given frames: forward + backward as
+ * gs_upsampler_grads, then one Adam update of every parameter (Kingma & Ba:
+ * beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected moments, the update
+ * count kept in the context) at learning rate lr >= 0. *loss_out (HOST,
+ * nullable) receives the loss before the update. Synchronous. */
+int gs_upsampler_step(gs_ctx *ctx, int32_t n, int32_t h, int32_t w, const float *rgb_lo,
+                      const float *depth_lo, const float *rgb_hi, const float *depth_hi,
+                      float lr, float *loss_out, void *stream);
+
+/* One Adam update (as in gs_upsampler_step) with a caller-given gradient:
+ * grads HOST [n] in the parameter-vector layout, n =
+ * gs_upsampler_num_params(). For optimising the network on gradients computed
+ * elsewhere. Synchronous. */
+int gs_upsampler_apply_grads(gs_ctx *ctx, const float *grads, int64_t n, float lr);
+
+/* Adam state: first and second moments (HOST [n] each, nullable) in the
+ * parameter-vector layout and the number of updates so far. Synchronous. */
+int gs_upsampler_get_state(gs_ctx *ctx, float *m, float *v, int64_t n, int32_t *step);
+
+/* Learning rate gs_upsampler_train uses at optimisation step `step` (0-based)
+ * of `steps`: lr_min + (lr0 - lr_min) (1 + cos(pi step / (steps - 1))) / 2,
+ * i.e. lr0 at the first step and lr_min at the last (lr0 when steps <= 1). */
+float gs_upsampler_lr(int32_t step, int32_t steps, float lr0, float lr_min);
+
+/* Fallback confidence score of n low-resolution frames (rgb_lo [n][h][w][3],
+ * depth_lo [n][h][w] DEVICE): for the network input (r, g, b, depth/10), the
+ * sum over channels of squared differences to the right and lower
+ * neighbours (where they exist), divided by h w. score_out DEVICE [n].
+ * Asynchronous on stream. gs_render_batch_upsampled scores its frames so. */
+int gs_upsampler_score(gs_ctx *ctx, int32_t n, int32_t h, int32_t w, const float *rgb_lo,
+                       const float *depth_lo, float *score_out, void *stream);
+
 /* Train on n_pairs cameras (scene_ids HOST, poses / full-res intrinsics
  * DEVICE): every step renders `batch` cameras at width x height (targets)
  * and at width/4 x height/4 (inputs) with the batched renderer, runs the
- * network forward and backward and applies Adam; cameras are taken in order,
- * wrapping around. loss_curve (HOST, `steps` values, nullable) receives each
- * step's loss. Synchronous. */
+ * network forward and backward and applies Adam at the learning rate
+ * gs_upsampler_lr(step, steps, lr, lr_min) (lr_min 0 means lr / 20);
+ * cameras are taken in order, wrapping around. loss_curve (HOST, `steps`
+ * values, nullable) receives each step's loss. Synchronous. */
 int gs_upsampler_train(gs_ctx *ctx, const gs_train_opts *opts, int32_t n_pairs,
                        const int32_t *scene_ids, const float *poses, const float *intrinsics,
                        int32_t width, int32_t height, float *loss_curve, void *stream);

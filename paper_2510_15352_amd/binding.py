@@ -29,8 +29,9 @@ EXPORTS = ("gs_abi_sizes", "gs_default_opts", "gs_create", "gs_destroy", "gs_las
            "gs_debug_project", "gs_autotune", "gs_set_instance_capacity", "gs_clear_graphs",
            "gs_upsampler_num_params", "gs_upsampler_init", "gs_upsampler_set_weights",
            "gs_upsampler_get_weights", "gs_upsampler_save", "gs_upsampler_load",
-           "gs_upsampler_forward", "gs_upsampler_grads",
-           "gs_upsampler_train", "gs_render_batch_upsampled", "gs_frame_psnr")
+           "gs_upsampler_forward", "gs_upsampler_grads", "gs_upsampler_step",
+           "gs_upsampler_apply_grads", "gs_upsampler_get_state", "gs_upsampler_lr",
+           "gs_upsampler_score", "gs_upsampler_train", "gs_render_batch_upsampled", "gs_frame_psnr")
 
 
 class GsError(RuntimeError):
@@ -116,6 +117,12 @@ def load():
     L.gs_upsampler_load.argtypes = [vp, ctypes.c_char_p]
     L.gs_upsampler_forward.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
     L.gs_upsampler_grads.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.gs_upsampler_step.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, fp, vp, vp]
+    L.gs_upsampler_apply_grads.argtypes = [vp, vp, i64, fp]
+    L.gs_upsampler_get_state.argtypes = [vp, vp, vp, i64, ctypes.POINTER(i32)]
+    L.gs_upsampler_lr.argtypes = [i32, i32, fp, fp]
+    L.gs_upsampler_lr.restype = fp
+    L.gs_upsampler_score.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
     L.gs_upsampler_train.argtypes = [vp, ctypes.POINTER(TrainOpts), i32, vp, vp, vp, i32, i32, vp,
                                      vp]
     L.gs_render_batch_upsampled.argtypes = [vp, i32, vp, vp, vp, i32, i32, vp, vp, vp,
@@ -366,7 +373,7 @@ class Renderer:
         n, h, w, _ = rgb_lo.shape
         rgb = torch.empty((n, 4 * h, 4 * w, 3), dtype=torch.float32, device=self.device)
         depth = torch.empty((n, 4 * h, 4 * w), dtype=torch.float32, device=self.device)
-        a, d = rgb_lo.contiguous(), depth_lo.contiguous()
+        a, d = self._dev(rgb_lo), self._dev(depth_lo)
         self._check(self.lib.gs_upsampler_forward(self.ctx, n, h, w, a.data_ptr(), d.data_ptr(),
                                                   rgb.data_ptr(), depth.data_ptr(),
                                                   _stream_ptr(torch)))
@@ -374,7 +381,7 @@ class Renderer:
 
     def up_grads(self, rgb_lo, depth_lo, rgb_hi, depth_hi):
         n, h, w, _ = rgb_lo.shape
-        tensors = [t.contiguous() for t in (rgb_lo, depth_lo, rgb_hi, depth_hi)]
+        tensors = [self._dev(t) for t in (rgb_lo, depth_lo, rgb_hi, depth_hi)]
         loss = ctypes.c_float()
         g = np.zeros(self.up_num_params(), np.float32)
         self._check(self.lib.gs_upsampler_grads(self.ctx, n, h, w,
@@ -382,6 +389,52 @@ class Renderer:
                                                 ctypes.byref(loss), g.ctypes.data,
                                                 _stream_ptr(self.torch)))
         return float(loss.value), g
+
+    def up_step(self, rgb_lo, depth_lo, rgb_hi, depth_hi, lr):
+        """One forward + backward + Adam step on given frames; returns the loss."""
+        n, h, w, _ = rgb_lo.shape
+        tensors = [self._dev(t) for t in (rgb_lo, depth_lo, rgb_hi, depth_hi)]
+        loss = ctypes.c_float()
+        self._check(self.lib.gs_upsampler_step(self.ctx, n, h, w, *[t.data_ptr() for t in tensors],
+                                               float(lr), ctypes.byref(loss),
+                                               _stream_ptr(self.torch)))
+        return float(loss.value)
+
+    def up_apply_grads(self, grads, lr):
+        """One Adam update with the given gradient (parameter-vector layout)."""
+        g = np.ascontiguousarray(np.asarray(grads, np.float32).reshape(-1))
+        self._check(self.lib.gs_upsampler_apply_grads(self.ctx, g.ctypes.data, len(g), float(lr)))
+
+    def up_state(self):
+        """Adam state: (first moments, second moments, update count)."""
+        n = self.up_num_params()
+        m = np.zeros(n, np.float32)
+        v = np.zeros(n, np.float32)
+        step = ctypes.c_int32()
+        self._check(self.lib.gs_upsampler_get_state(self.ctx, m.ctypes.data, v.ctypes.data, n,
+                                                    ctypes.byref(step)))
+        return m, v, int(step.value)
+
+    def up_lr(self, step, steps, lr0, lr_min):
+        return float(self.lib.gs_upsampler_lr(int(step), int(steps), float(lr0), float(lr_min)))
+
+    def up_score(self, rgb_lo, depth_lo):
+        """Fallback confidence score of low-resolution frames (device tensor [n])."""
+        torch = self.torch
+        n, h, w, _ = rgb_lo.shape
+        a, d = self._dev(rgb_lo), self._dev(depth_lo)
+        out = torch.empty(n, dtype=torch.float32, device=self.device)
+        self._check(self.lib.gs_upsampler_score(self.ctx, n, h, w, a.data_ptr(), d.data_ptr(),
+                                                out.data_ptr(), _stream_ptr(torch)))
+        return out
+
+    def _dev(self, a):
+        """A contiguous float32 tensor on the context's device (copied when needed)."""
+        torch = self.torch
+        if (torch.is_tensor(a) and a.device == self.device and a.dtype == torch.float32
+                and a.is_contiguous()):
+            return a
+        return _dev_f32(torch, a, self.device)
 
     def up_train(self, scene_ids, poses, intrinsics, width, height, batch=32, steps=100, lr=1e-3,
                  lr_min=0.0):
@@ -403,9 +456,9 @@ class Renderer:
         torch = self.torch
         sids = np.ascontiguousarray(np.asarray(scene_ids, dtype=np.int32).reshape(-1))
         n = len(sids)
-        P = poses if (torch.is_tensor(poses) and poses.is_cuda) else _dev_f32(torch, poses, self.device)
-        K = intrinsics if (torch.is_tensor(intrinsics) and intrinsics.is_cuda) \
-            else _dev_f32(torch, intrinsics, self.device)
+        P, K = self._dev(poses), self._dev(intrinsics)
+        if P.numel() != n * 12 or K.numel() != n * 4:
+            raise ValueError("poses must be [n,3,4] and intrinsics [n,4]")
         rgb, depth, _ = out if out is not None else self.alloc_outputs(n, width, height, alpha=False)
         score = torch.empty(n, dtype=torch.float32, device=self.device)
         nf = ctypes.c_int32()

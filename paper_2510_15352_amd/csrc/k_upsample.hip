@@ -17,6 +17,8 @@
 //   weight grad  dW[co][t][ci] = sum_p dY[p][co] X[p + off(t)][ci]: M = 16 co,
 //                N = 16 (t, ci), K = 32 pixels; one partial per block, summed
 //                in a fixed order by a second kernel (deterministic).
+#include <cmath>
+
 #include "gs_device.h"
 #include "up_kernels.h"
 
@@ -501,16 +503,17 @@ __global__ void k_pack_weights(const float *__restrict__ w, int cout, int cin, i
     if (wd && ci < cin) wd[((8 - t) * cin + ci) * cout + co] = bf16_bits(v);
 }
 
-// Adam with bias correction; p, m, v, g FP32.
+// Adam with bias correction; p, m, v, g FP32. omb1 = 1 - b1 and omb2 = 1 - b2
+// come rounded from their exact values (1 - fl32(0.999) is 1.3e-5 off).
 __global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
                        const float *__restrict__ g, int n, float lr, float b1, float b2,
-                       float eps, float c1, float c2)
+                       float omb1, float omb2, float eps, float c1, float c2)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    const float mi = b1 * m[i] + omb1 * gi;
+    const float vi = b2 * v[i] + omb2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
     p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
@@ -668,11 +671,12 @@ void launch_pack_weights(const float *w, int cout, int cin, int cinp, uint16_t *
 void launch_adam(float *p, float *m, float *v, const float *g, int n, float lr, int step,
                  hipStream_t st)
 {
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const float c1 = 1.0f / (1.0f - powf(b1, (float)step));
-    const float c2 = 1.0f / (1.0f - powf(b2, (float)step));
-    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, st, p, m, v, g, n, lr, b1, b2,
-                       eps, c1, c2);
+    // Kingma & Ba defaults; the bias corrections 1 / (1 - b^step) in FP64
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(b2, (double)step)));
+    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, st, p, m, v, g, n, lr,
+                       (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f, c1, c2);
 }
 
 void launch_up_score(const float *x0f, int n, int h, int w, float *score, hipStream_t st)

@@ -913,6 +913,31 @@ void up_adam(gs_ctx *ctx, float lr, hipStream_t st)
     U.packed = false;
 }
 
+// Cosine learning-rate schedule of the optimisation steps: lr0 at step 0,
+// lr_min at step steps - 1 (half a cosine period), lr0 throughout for one step.
+float up_cosine_lr(int s, int steps, float lr0, float lr_min)
+{
+    if (steps <= 1) return lr0;
+    const double pi = 3.14159265358979323846;
+    return (float)((double)lr_min + 0.5 * ((double)lr0 - (double)lr_min) *
+                                        (1.0 + std::cos(pi * (double)s / (double)(steps - 1))));
+}
+
+// Confidence scores of n low-resolution frames, in chunks of the network's
+// activation buffers.
+void up_scores(gs_ctx *ctx, int n, int h, int w, const float *rgb_lo, const float *depth_lo,
+               float *score, hipStream_t st)
+{
+    Upsampler &U = ctx->up;
+    const int64_t lp = (int64_t)h * w;
+    for (int c0 = 0; c0 < n; c0 += kUpChunk) {
+        const int m = std::min(kUpChunk, n - c0);
+        up_alloc(ctx, m, h, w, false);
+        launch_up_input(rgb_lo + c0 * lp * 3, depth_lo + c0 * lp, m * lp, U.x0f.p, nullptr, st);
+        launch_up_score(U.x0f.p, m, h, w, score + c0, st);
+    }
+}
+
 uint64_t splitmix(uint64_t &x)
 {
     uint64_t z = (x += 0x9E3779B97F4A7C15ull);
@@ -1652,6 +1677,82 @@ int gs_upsampler_grads(gs_ctx *ctx, int32_t n, int32_t h, int32_t w, const float
     });
 }
 
+int gs_upsampler_step(gs_ctx *ctx, int32_t n, int32_t h, int32_t w, const float *rgb_lo,
+                      const float *depth_lo, const float *rgb_hi, const float *depth_hi,
+                      float lr, float *loss_out, void *stream)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (n < 1 || h < 1 || w < 1 || !rgb_lo || !depth_lo || !rgb_hi || !depth_hi)
+        return fail(ctx, GS_ERR_INVALID_ARG, "bad upsampler step arguments");
+    if (!(lr >= 0.0f) || !std::isfinite(lr))
+        return fail(ctx, GS_ERR_INVALID_ARG, "lr must be a finite value >= 0");
+    if (!ctx->up.ready) return fail(ctx, GS_ERR_NOT_TRAINED, "upsampler not initialised");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        hipStream_t st = (hipStream_t)stream;
+        const float loss = up_loss_and_grads(ctx, n, h, w, rgb_lo, depth_lo, rgb_hi, depth_hi, st);
+        up_adam(ctx, lr, st);
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipStreamSynchronize(st));
+        if (loss_out) *loss_out = loss;
+        return GS_OK;
+    });
+}
+
+int gs_upsampler_apply_grads(gs_ctx *ctx, const float *grads, int64_t n, float lr)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (!grads || n != up_num_params())
+        return fail(ctx, GS_ERR_INVALID_ARG, "gradient vector must hold gs_upsampler_num_params() values");
+    if (!(lr >= 0.0f) || !std::isfinite(lr))
+        return fail(ctx, GS_ERR_INVALID_ARG, "lr must be a finite value >= 0");
+    if (!ctx->up.ready) return fail(ctx, GS_ERR_NOT_TRAINED, "upsampler not initialised");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        HIP_CHECK(hipDeviceSynchronize());
+        up_put(ctx->up.gw, ctx->up.gb, grads);
+        up_adam(ctx, lr, nullptr);
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipDeviceSynchronize());
+        return GS_OK;
+    });
+}
+
+int gs_upsampler_get_state(gs_ctx *ctx, float *m, float *v, int64_t n, int32_t *step)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (n != up_num_params())
+        return fail(ctx, GS_ERR_INVALID_ARG, "moment vectors must hold gs_upsampler_num_params() values");
+    if (!ctx->up.ready) return fail(ctx, GS_ERR_NOT_TRAINED, "upsampler not initialised");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        HIP_CHECK(hipDeviceSynchronize());
+        if (m) up_get(ctx, ctx->up.mw, ctx->up.mb, m);
+        if (v) up_get(ctx, ctx->up.vw, ctx->up.vb, v);
+        if (step) *step = ctx->up.step;
+        return GS_OK;
+    });
+}
+
+float gs_upsampler_lr(int32_t step, int32_t steps, float lr0, float lr_min)
+{
+    return up_cosine_lr(step, steps, lr0, lr_min);
+}
+
+int gs_upsampler_score(gs_ctx *ctx, int32_t n, int32_t h, int32_t w, const float *rgb_lo,
+                       const float *depth_lo, float *score_out, void *stream)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (n < 1 || h < 1 || w < 1 || !rgb_lo || !depth_lo || !score_out)
+        return fail(ctx, GS_ERR_INVALID_ARG, "bad score arguments");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        up_scores(ctx, n, h, w, rgb_lo, depth_lo, score_out, (hipStream_t)stream);
+        HIP_CHECK(hipGetLastError());
+        return GS_OK;
+    });
+}
+
 int gs_upsampler_train(gs_ctx *ctx, const gs_train_opts *opts, int32_t n_pairs,
                        const int32_t *scene_ids, const float *poses, const float *intrinsics,
                        int32_t width, int32_t height, float *loss_curve, void *stream)
@@ -1690,10 +1791,7 @@ int gs_upsampler_train(gs_ctx *ctx, const gs_train_opts *opts, int32_t n_pairs,
             if (rc) return rc;
             const float loss = up_loss_and_grads(ctx, batch, h, w, U.lo_rgb.p, U.lo_depth.p,
                                                  U.hi_rgb.p, U.hi_depth.p, st);
-            const float lr = lr1 + 0.5f * (lr0 - lr1) *
-                                       (1.0f + std::cos(3.14159265f * (float)s /
-                                                        (float)std::max(opts->steps - 1, 1)));
-            up_adam(ctx, lr, st);
+            up_adam(ctx, up_cosine_lr(s, opts->steps, lr0, lr1), st);
             if (loss_curve) loss_curve[s] = loss;
         }
         HIP_CHECK(hipStreamSynchronize(st));

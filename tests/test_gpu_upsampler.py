@@ -170,3 +170,173 @@ def test_checkpoint_restores_training_state_exactly(gpu_renderer, tmp_path):
         other.close()
     gpu_renderer.release_scene(sid)
     assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------ training step --
+
+def _per_layer(vec):
+    """Split a parameter vector into per-layer (weights, bias) slices."""
+    out, off = [], 0
+    for li in range(4):
+        ci, co = U.CH[li], U.CH[li + 1]
+        nw = co * 9 * ci
+        out.append((vec[off:off + nw], vec[off + nw:off + nw + co]))
+        off += nw + co
+    return out
+
+
+def test_adam_update_matches_oracle(gpu_renderer):
+    """k_adam against the oracle's Adam on the same seeded FP32 gradients
+    (three updates, changing learning rates): parameters, both moments and
+    the update count, to FP32 rounding."""
+    _, p0 = _random_params(40)
+    gpu_renderer.up_set(p0)
+    rng = np.random.default_rng(41)
+    p, m, v = p0.astype(np.float64), np.zeros(p0.size), np.zeros(p0.size)
+    for step, lr in enumerate((1e-3, 3e-3, 5e-4), start=1):
+        g = (rng.normal(size=p0.size) * 10.0 ** rng.uniform(-4, 0, size=p0.size)).astype(np.float32)
+        gpu_renderer.up_apply_grads(g, lr)
+        p, m, v = U.adam_step(p, g.astype(np.float64), m, v, step, lr)
+    gp = gpu_renderer.up_get().astype(np.float64)
+    gm, gv, gstep = gpu_renderer.up_state()
+    assert gstep == 3
+    np.testing.assert_allclose(gm, m, rtol=2e-6, atol=0)
+    np.testing.assert_allclose(gv, v, rtol=2e-6, atol=0)
+    # per element: the parameter's own rounding plus the update's (lr scale)
+    np.testing.assert_allclose(gp, p, rtol=2e-7, atol=1e-5 * 5e-3)
+    print(f"adam: max |dp| {np.abs(gp - p).max():.2e}, max rel m {np.abs(gm / m - 1).max():.2e}")
+
+
+def test_training_steps_match_oracle(gpu_renderer):
+    """Three forward + backward + Adam steps on given frames against the
+    FP64 oracle's train_step. The GPU gradients are BF16 MFMA products
+    (bounded at relative L2 3e-2 per layer by the gradient test), so the
+    first moments, linear in the gradients, are held to 3e-2 per layer and
+    the second moments, quadratic, to 6e-2; the parameters (initial values
+    plus three updates) to 1e-3 over the vector, and the update direction of
+    every layer to a cosine of 0.97."""
+    import torch
+    params, p0 = _random_params(42)
+    gpu_renderer.up_set(p0)
+    n, h, w = 2, 12, 20
+    rgb, depth = _inputs(n, h, w, 43)
+    rng = np.random.default_rng(44)
+    t_rgb = rng.uniform(0, 1, size=(n, 4 * h, 4 * w, 3)).astype(np.float32)
+    t_d = rng.uniform(1, 20, size=(n, 4 * h, 4 * w)).astype(np.float32)
+    dev = [torch.as_tensor(a).cuda() for a in (rgb, depth, t_rgb, t_d)]
+    x0 = U.make_input(rgb.astype(np.float64), depth.astype(np.float64))
+    target = U.make_input(t_rgb.astype(np.float64), t_d.astype(np.float64))
+    p, m, v = p0.astype(np.float64), np.zeros(p0.size), np.zeros(p0.size)
+    for step, lr in enumerate((2e-3, 1e-3, 5e-4), start=1):
+        loss = gpu_renderer.up_step(*dev, lr)
+        ref_loss, p, m, v = U.train_step(p, m, v, step, x0, target, lr)
+        assert loss == pytest.approx(ref_loss, rel=1e-2), step
+    gp = gpu_renderer.up_get().astype(np.float64)
+    gm, gv, gstep = gpu_renderer.up_state()
+    assert gstep == 3
+    assert _rel_l2(gp, p) < 1e-3
+    for li, ((a_m, _), (b_m, _), (a_v, _), (b_v, _), (a_p, _), (b_p, _), (o_p, _)) in enumerate(
+            zip(_per_layer(gm), _per_layer(m), _per_layer(gv), _per_layer(v), _per_layer(gp),
+                _per_layer(p), _per_layer(p0.astype(np.float64)))):
+        em, ev = _rel_l2(a_m, b_m), _rel_l2(a_v, b_v)
+        du, dr = a_p - o_p, b_p - o_p
+        cos = float(du @ dr / (np.linalg.norm(du) * np.linalg.norm(dr)))
+        print(f"layer {li + 1}: m rel L2 {em:.2e}, v rel L2 {ev:.2e}, update cosine {cos:.4f}")
+        assert em < 3e-2 and ev < 6e-2 and cos > 0.97
+
+
+def test_learning_rate_schedule_matches_oracle(gpu_renderer):
+    for steps, lr0, lr1 in ((1, 1e-3, 1e-4), (2, 2e-3, 0.0), (9, 2e-3, 1e-4), (1562, 2e-3, 1e-4)):
+        for s in sorted({0, 1, steps // 3, steps // 2, steps - 2, steps - 1} - {-1}):
+            if s < 0 or s >= steps:
+                continue
+            assert gpu_renderer.up_lr(s, steps, lr0, lr1) == pytest.approx(
+                U.cosine_lr(s, steps, lr0, lr1), rel=1e-6, abs=1e-12), (steps, s)
+
+
+def test_confidence_score_matches_oracle(gpu_renderer):
+    import torch
+    for (n, h, w, seed) in ((3, 17, 23, 45), (1, 1, 1, 46), (2, 120, 160, 47)):
+        rgb, depth = _inputs(n, h, w, seed)
+        got = gpu_renderer.up_score(torch.as_tensor(rgb).cuda(), torch.as_tensor(depth).cuda())
+        ref = U.confidence_score(U.make_input(rgb.astype(np.float64), depth.astype(np.float64)))
+        np.testing.assert_allclose(got.cpu().numpy(), ref, rtol=2e-5, atol=1e-12)
+
+
+# --------------------------------------------- what the trained network gains --
+
+@pytest.fixture(scope="module")
+def trained(gpu_renderer):
+    """The network trained on the GPU (its own forward and backward kernels,
+    Adam) on seeded 640x480 / 160x120 pairs of the 200k-Gaussian SH-3 terrain
+    scene, with poses disjoint from the evaluation cameras. Yields (scene,
+    scene id, bilinear parameters, trained parameters)."""
+    sc = scenegen.make_scene(1)
+    sid = gpu_renderer.upload_scene(sc)
+    gpu_renderer.up_init(0)
+    bilinear = gpu_renderer.up_get()
+    train = scenegen.sampled_cameras(1, 2048, seed=1)
+    curve = gpu_renderer.up_train([sid] * 2048, train["poses"], train["intrinsics"], 640, 480,
+                                  batch=16, steps=128, lr=2e-3, lr_min=1e-4)
+    print(f"trained 128 x 16 pairs: loss {curve[:8].mean():.5f} -> {curve[-8:].mean():.5f}")
+    yield sc, sid, bilinear, gpu_renderer.up_get()
+    gpu_renderer.release_scene(sid)
+
+
+def test_trained_network_beats_bilinear_on_held_out_cameras(gpu_renderer, trained):
+    """The method without the network is bilinear upsampling of the
+    low-resolution render (the untrained network is exactly that). On 64
+    held-out cameras the trained network must gain at least 1 dB of mean
+    PSNR against the full-resolution render, and win on most frames."""
+    sc, sid, bilinear, weights = trained
+    ev = scenegen.make_cameras(1)
+    ids = [sid] * 64
+    full = gpu_renderer.render(ids, ev["poses"], ev["intrinsics"], 640, 480, alpha=False)
+    gpu_renderer.up_set(bilinear)
+    up_b = gpu_renderer.render_upsampled(ids, ev["poses"], ev["intrinsics"], 640, 480)
+    p_b = gpu_renderer.frame_psnr(up_b[0], full[0]).cpu().numpy()
+    gpu_renderer.up_set(weights)
+    up_t = gpu_renderer.render_upsampled(ids, ev["poses"], ev["intrinsics"], 640, 480)
+    p_t = gpu_renderer.frame_psnr(up_t[0], full[0]).cpu().numpy()
+    gain = p_t - p_b
+    print(f"held-out PSNR: bilinear {p_b.mean():.2f} dB, trained {p_t.mean():.2f} dB, "
+          f"gain mean {gain.mean():.2f} min {gain.min():.2f}, frames improved "
+          f"{(gain > 0).mean():.2f}")
+    assert gain.mean() >= 1.0
+    assert (gain > 0).mean() >= 0.9
+
+
+def test_learned_form_against_the_oracle(gpu_renderer, trained):
+    """The learned form judged by the FP64 oracle on 128 seeded held-out
+    frames: PSNR and max-abs RGB error of the upsampled frames, next to the
+    bilinear upsampling of the same low-resolution renders; frames that fall
+    back are the full-resolution render and must pass the oracle comparator."""
+    import oracle
+    sc, sid, bilinear, weights = trained
+    cams = scenegen.sampled_cameras(1, 128, seed=7)
+    ids = [sid] * 128
+    P, K = cams["poses"], cams["intrinsics"]
+    gpu_renderer.up_set(weights)
+    rgb_t, _, score, _ = gpu_renderer.render_upsampled(ids, P, K, 640, 480)
+    gpu_renderer.up_set(bilinear)
+    rgb_b = gpu_renderer.render_upsampled(ids, P, K, 640, 480)[0]
+    rgb_t, rgb_b = rgb_t.cpu().numpy(), rgb_b.cpu().numpy()
+    refs = np.stack([oracle.render(sc, P[c], K[c], 640, 480).rgb for c in range(128)])
+    p_t = U.psnr(rgb_t.astype(np.float64), refs)
+    p_b = U.psnr(rgb_b.astype(np.float64), refs)
+    e_t = np.abs(np.clip(rgb_t, 0, 1) - np.clip(refs, 0, 1)).reshape(128, -1).max(axis=1)
+    print(f"vs oracle, 128 frames: trained PSNR mean {p_t.mean():.2f} p5 "
+          f"{np.percentile(p_t, 5):.2f} dB (bilinear {p_b.mean():.2f}); max-abs RGB median "
+          f"{np.median(e_t):.3f} max {e_t.max():.3f}")
+    assert p_t.mean() >= p_b.mean() + 1.0
+    # fallback of the four highest-scoring frames: the full-resolution render
+    thr = float(np.sort(score.cpu().numpy())[-5])
+    gpu_renderer.up_set(weights)
+    rgb_f, depth_f, score_f, nf = gpu_renderer.render_upsampled(ids[:128], P, K, 640, 480,
+                                                               threshold=thr)
+    flagged = np.nonzero(~(score_f.cpu().numpy() <= thr))[0]
+    assert nf == len(flagged) == 4
+    for c in flagged:
+        ref = oracle.render(sc, P[c], K[c], 640, 480)
+        rep = oracle.compare(ref, rgb_f[c].cpu().numpy(), depth_f[c].cpu().numpy())
+        assert rep["failed"] == 0, (c, rep)
