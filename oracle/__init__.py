@@ -245,8 +245,10 @@ def compare(ref: Render, rgb, depth, alpha=None) -> dict:
     A pixel passes when it is within tolerance of the FP64 result (max-abs
     RGB 2e-3, relative depth 1e-3, max-abs alpha 2e-3), or of one of the
     alternatives the oracle lists for that pixel. Returns a report with the
-    raw maxima, the number of pixels accepted through an alternative and the
-    number that failed."""
+    raw maxima, the maxima over the pixels that have no alternative
+    (plain_*: only rounding separates the results there), the number of
+    pixels with alternatives, flagged and unresolved by the oracle, accepted
+    through an alternative (rescued) and failed."""
     rgb = np.asarray(rgb, np.float64)
     depth = np.asarray(depth, np.float64)
     alpha = ref.alpha if alpha is None else np.asarray(alpha, np.float64)
@@ -271,8 +273,20 @@ def compare(ref: Render, rgb, depth, alpha=None) -> dict:
                 flat_ok[p] = True
                 rescued += 1
     failed = int((~flat_ok).sum())
+    # pixels for which the oracle lists no alternative: every decision there
+    # is clear of its threshold, so only rounding separates the two results
+    plain = np.ones(H * W, bool)
+    plain[np.unique(ref.var_pix)] = False
+    plain = plain.reshape(H, W)
+
+    def pmax(e):
+        return float(e[plain].max()) if plain.any() else 0.0
     return dict(max_abs_rgb=float(e_rgb.max()) if e_rgb.size else 0.0,
                 max_rel_depth=float(e_dep.max()) if e_dep.size else 0.0,
                 max_abs_alpha=float(e_alp.max()) if e_alp.size else 0.0,
+                plain_max_abs_rgb=pmax(e_rgb), plain_max_rel_depth=pmax(e_dep),
+                plain_max_abs_alpha=pmax(e_alp),
+                with_alternatives=int(H * W - plain.sum()),
+                flagged=int(ref.counters["flagged"]), unresolved=int(ref.counters["unresolved"]),
                 rescued=rescued, failed=failed, pixels=H * W,
                 failed_pixels=np.nonzero(~flat_ok)[0][:20].tolist())

@@ -32,10 +32,12 @@
  * wherever the margin exceeds rounding.
  *
  * Several results are correct where a decision sits at its threshold within
- * rounding (skip at 1/255, stop at 1e-4, the near plane, two contributors at
- * the same depth). For such pixels the oracle additionally enumerates every
- * combination of those decisions (bounded) and reports the alternative
- * results, so a comparator can accept a GPU value matching any of them.
+ * rounding (skip at 1/255, stop at 1e-4, the near plane, contributors at
+ * nearly the same depth). For such pixels the oracle additionally enumerates
+ * every combination of those decisions and every order of each run of up to
+ * four near-tied contributors (bounded; beyond the bound the pixel is counted
+ * as unresolved) and reports the alternative results, so a comparator can
+ * accept a GPU value matching any of them.
  */
 #include <math.h>
 #include <stdint.h>
@@ -323,15 +325,17 @@ typedef struct {
     int max_leaves;
 } walk_cfg_t;
 
+#define MAX_LEAVES 256
+
 typedef struct {
     int n;
     int overflow;
-    double v[64][5];
+    double v[MAX_LEAVES][5];
 } leaves_t;
 
 static void emit_leaf(leaves_t *L, const walk_cfg_t *cfg, double T, const double acc[5])
 {
-    if (L->n >= cfg->max_leaves || L->n >= 64) { L->overflow = 1; return; }
+    if (L->n >= cfg->max_leaves || L->n >= MAX_LEAVES) { L->overflow = 1; return; }
     double *v = L->v[L->n++];
     v[0] = acc[0] + T * cfg->bg[0];
     v[1] = acc[1] + T * cfg->bg[1];
@@ -397,6 +401,30 @@ static void walk_branching(const cand_t *c, const int *order, int n, int i, doub
         T = T * (1.0 - k->alpha);
     }
     emit_leaf(L, cfg, T, acc);
+}
+
+/* Near-tie runs: at most MAX_RUNS runs of at most MAX_RUN_LEN members and
+ * MAX_ORDERS orders in all per pixel (else the pixel is unresolved). */
+#define MAX_RUNS 8
+#define MAX_RUN_LEN 4
+#define MAX_ORDERS 48
+
+/* Rearrange p[0..len) into its k-th permutation in lexicographic order
+ * (k < len!, decoded as a factorial-base number). */
+static void run_order(int *p, int len, long k)
+{
+    int pool[MAX_RUN_LEN], out[MAX_RUN_LEN];
+    for (int i = 0; i < len; ++i) pool[i] = p[i];
+    int left = len;
+    for (int i = 0; i < len; ++i) {
+        long f = (long)factorial(len - 1 - i);
+        int sel = (int)(k / f);
+        k %= f;
+        out[i] = pool[sel];
+        for (int j = sel; j + 1 < left; ++j) pool[j] = pool[j + 1];
+        --left;
+    }
+    for (int i = 0; i < len; ++i) p[i] = out[i];
 }
 
 /* Step 6 with the natural FP64 decisions only. Returns the contributor count;
@@ -510,7 +538,7 @@ int gso_render(const float *means, const float *scales, const float *quats,
         if (live[g])
             for (int y = pb[g * 4 + 2]; y <= pb[g * 4 + 3]; ++y) row_g[fill[y]++] = (int32_t)g;
 
-    walk_cfg_t cfg = {{bg[0], bg[1], bg[2]}, eps_alpha, eps_T, 64};
+    walk_cfg_t cfg = {{bg[0], bg[1], bg[2]}, eps_alpha, eps_T, MAX_LEAVES};
     int64_t n_pairs = 0, n_flag = 0, n_unres = 0, n_cand = 0, var_count = 0;
 
 #pragma omp parallel reduction(+ : n_pairs, n_flag, n_unres, n_cand)
@@ -558,31 +586,44 @@ int gso_render(const float *means, const float *scales, const float *quats,
                 n_pairs += nc;
                 rgb[pix * 3 + 0] = out[0]; rgb[pix * 3 + 1] = out[1]; rgb[pix * 3 + 2] = out[2];
                 depth[pix] = out[3]; alpha[pix] = out[4]; tfinal[pix] = T;
-                /* depth near-ties between neighbours in the (z, index) order, among
-                 * the candidates the walk reaches: past the stop, any reordering
-                 * changes the pixel by less than the final transmittance (< 1e-4
-                 * times the largest colour). */
-                int ties[8], nt = 0;
-                for (int i = 0; i + 1 < cn && i < reach; ++i)
-                    if (fabs(c[i + 1].z - c[i].z) <= eps_z) {
-                        if (nt < 8) ties[nt] = i;
-                        ++nt;
+                /* Runs of near-tied depths in the (z, index) order (consecutive
+                 * gaps within eps_z) that start among the candidates the walk
+                 * reaches: every order of such a run is a correct result, since
+                 * rounding may order its members either way. Past the stop, any
+                 * reordering changes the pixel by less than the final
+                 * transmittance (< 1e-4 times the largest colour). */
+                int run_s[MAX_RUNS], run_n[MAX_RUNS], nr = 0, unres = 0;
+                long n_orders = 1;
+                for (int i = 0; i + 1 < cn && i < reach;) {
+                    if (!(fabs(c[i + 1].z - c[i].z) <= eps_z)) { ++i; continue; }
+                    int j = i + 1;
+                    while (j + 1 < cn && fabs(c[j + 1].z - c[j].z) <= eps_z) ++j;
+                    if (j - i + 1 > MAX_RUN_LEN || nr == MAX_RUNS) {
+                        unres = 1;
+                    } else {
+                        run_s[nr] = i;
+                        run_n[nr] = j - i + 1;
+                        n_orders *= (long)factorial(run_n[nr]);
+                        ++nr;
                     }
-                if (!marginal && nt == 0) { s = e; continue; }
+                    i = j + 1;
+                }
+                if (!marginal && nr == 0 && !unres) { s = e; continue; }
                 ++n_flag;
-                if (nt > 6) { ++n_unres; s = e; continue; }
+                if (unres || n_orders > MAX_ORDERS) { ++n_unres; s = e; continue; }
                 if (cn > order_cap) {
                     order_cap = cn * 2;
                     order = (int *)realloc(order, sizeof(int) * order_cap);
                 }
                 L->n = 0; L->overflow = 0;
-                for (int mask = 0; mask < (1 << nt); ++mask) {
+                for (long k = 0; k < n_orders; ++k) {
                     for (int i = 0; i < cn; ++i) order[i] = i;
-                    for (int t = 0; t < nt; ++t)
-                        if (mask >> t & 1) {
-                            int i = ties[t], tmp = order[i];
-                            order[i] = order[i + 1]; order[i + 1] = tmp;
-                        }
+                    long rem = k;
+                    for (int r = 0; r < nr; ++r) {
+                        long f = (long)factorial(run_n[r]);
+                        run_order(order + run_s[r], run_n[r], rem % f);
+                        rem /= f;
+                    }
                     double acc0[5] = {0, 0, 0, 0, 0};
                     walk_branching(c, order, cn, 0, 1.0, acc0, &cfg, L);
                 }

@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 import scenegen
+from test_gpu_parity import _check
 
 pytestmark = pytest.mark.gpu
 
@@ -44,11 +45,8 @@ def _run(gpu_renderer, k, step, n_sample, seed):
     for c in pick:
         ref = oracle.render(scenes[int(cams["scene_ids"][c])], cams["poses"][c],
                             cams["intrinsics"][c], W, H)
-        rep = oracle.compare(ref, rgb[c].cpu().numpy(), depth[c].cpu().numpy(),
-                             alpha[c].cpu().numpy())
-        print(f"w{k} step {step} cam {c}: max|rgb| {rep['max_abs_rgb']:.2e} rel depth "
-              f"{rep['max_rel_depth']:.2e} rescued {rep['rescued']} failed {rep['failed']}",
-              flush=True)
+        rep = _check(ref, rgb[c].cpu().numpy(), depth[c].cpu().numpy(),
+                     alpha[c].cpu().numpy(), f"w{k} step {step} cam {c}")
         fails += rep["failed"]
     st = gpu_renderer.stats()
     gpu_renderer.drop_graphs()

@@ -239,3 +239,73 @@ def test_near_tie_before_stop_listed_despite_ties_after_stop():
     assert len(rows) >= 2
     # one alternative puts the blue Gaussian first: more blue than the primary
     assert any(v[2] - r.rgb[24, 32, 2] > 1e-2 for v in rows)
+
+
+def _walk_in_order(rec, order, W, H):
+    """Per-pixel walk (skip, stop, accumulate) over the Gaussians in a given
+    order, FP64, from the projection records."""
+    out = np.zeros((H, W, 5))
+    for j in range(H):
+        for i in range(W):
+            T, acc = 1.0, np.zeros(5)
+            for g in order:
+                dx, dy = i + 0.5 - rec["u"][g], j + 0.5 - rec["v"][g]
+                q = rec["conic_a"][g] * dx * dx + 2 * rec["conic_b"][g] * dx * dy + \
+                    rec["conic_c"][g] * dy * dy
+                a = min(AMAX, rec["opacity"][g] * math.exp(-q / 2))
+                if a < AMIN:
+                    continue
+                if T * (1 - a) < TMIN:
+                    break
+                w = a * T
+                acc += w * np.array([rec["r"][g], rec["g"][g], rec["b"][g], rec["z"][g], 1.0])
+                T *= 1 - a
+            out[j, i, :3] = acc[:3]
+            out[j, i, 3] = acc[3] / acc[4] if acc[4] > 0 else 0.0
+            out[j, i, 4] = acc[4]
+    return out
+
+
+def _tied_scene(k):
+    """k Gaussians at exactly the same depth in front of the camera, slightly
+    offset sideways, with distinct colours."""
+    Y00 = 1.0 / (2.0 * math.sqrt(math.pi))
+    rng = np.random.default_rng(70 + k)
+    cols = rng.uniform(0, 1, size=(k, 3))
+    means = np.array([[0.02 * g, -0.015 * g, 3.0] for g in range(k)], np.float32)
+    return dict(means=means, scales=np.full((k, 3), 0.2, np.float32),
+                quats=np.tile(np.array([1, 0, 0, 0], np.float32), (k, 1)),
+                opacity=np.full(k, 0.45, np.float32),
+                sh=((cols - 0.5) / Y00).astype(np.float32).reshape(k, 1, 3), sh_degree=0)
+
+
+def test_every_order_of_a_tied_run_is_accepted():
+    """Three contributors at exactly the same depth: the oracle walks them in
+    index order, and the comparator accepts an image composited in any of the
+    six orders (full reversal included)."""
+    import itertools
+    sc = _tied_scene(3)
+    W, H, intr = 16, 12, [20.0, 20.0, 8.0, 6.0]
+    r = oracle.render(sc, IDENT_POSE, intr, W, H)
+    rec = oracle.project_all(sc, IDENT_POSE, intr, W, H)
+    assert r.counters["unresolved"] == 0
+    for perm in itertools.permutations(range(3)):
+        img = _walk_in_order(rec, list(perm), W, H)
+        rep = oracle.compare(r, img[..., :3], img[..., 3], img[..., 4])
+        assert rep["failed"] == 0, (perm, rep)
+        if perm != (0, 1, 2):
+            assert rep["rescued"] > 0, perm
+    # a wrong colour at a tied pixel is still rejected
+    img = _walk_in_order(rec, [2, 1, 0], W, H)
+    img[6, 8, 0] += 0.05
+    assert oracle.compare(r, img[..., :3], img[..., 3], img[..., 4])["failed"] == 1
+
+
+def test_tied_run_beyond_the_bound_is_unresolved():
+    """Five contributors tied in depth exceed the four-member bound: those
+    pixels are counted as unresolved and list no alternative."""
+    sc = _tied_scene(5)
+    r = oracle.render(sc, IDENT_POSE, [20.0, 20.0, 8.0, 6.0], 16, 12)
+    assert r.counters["unresolved"] > 0
+    rep = oracle.compare(r, r.rgb, r.depth, r.alpha)
+    assert rep["failed"] == 0 and rep["unresolved"] == r.counters["unresolved"]
