@@ -325,7 +325,7 @@ typedef struct {
     int max_leaves;
 } walk_cfg_t;
 
-#define MAX_LEAVES 256
+#define MAX_LEAVES 1024
 
 typedef struct {
     int n;
@@ -407,7 +407,7 @@ static void walk_branching(const cand_t *c, const int *order, int n, int i, doub
  * MAX_ORDERS orders in all per pixel (else the pixel is unresolved). */
 #define MAX_RUNS 8
 #define MAX_RUN_LEN 4
-#define MAX_ORDERS 48
+#define MAX_ORDERS 256
 
 /* Rearrange p[0..len) into its k-th permutation in lexicographic order
  * (k < len!, decoded as a factorial-base number). */
