@@ -230,11 +230,13 @@ ALPHA_TOL = 2e-3    # max-abs accumulated weight
 
 
 def _pixel_errors(ref_rgb, ref_depth, ref_alpha, rgb, depth, alpha):
+    """Per-pixel errors; alpha None means the image has no alpha channel, so
+    only RGB and depth are held to their tolerances."""
     e_rgb = np.max(np.abs(rgb - ref_rgb), axis=-1)
     has = ref_alpha > 0
     e_dep = np.where(has, np.abs(depth - ref_depth) / np.where(has, np.abs(ref_depth), 1.0),
                      np.abs(depth))
-    e_alp = np.abs(alpha - ref_alpha)
+    e_alp = np.zeros_like(e_dep) if alpha is None else np.abs(alpha - ref_alpha)
     ok = (e_rgb <= RGB_TOL) & (e_dep <= DEPTH_TOL) & (e_alp <= ALPHA_TOL)
     return ok, e_rgb, e_dep, e_alp
 
@@ -244,14 +246,16 @@ def compare(ref: Render, rgb, depth, alpha=None) -> dict:
 
     A pixel passes when it is within tolerance of the FP64 result (max-abs
     RGB 2e-3, relative depth 1e-3, max-abs alpha 2e-3), or of one of the
-    alternatives the oracle lists for that pixel. Returns a report with the
+    alternatives the oracle lists for that pixel. Without `alpha` only RGB
+    and depth are compared (an alternative differs from the FP64 result in
+    its accumulated weight too). Returns a report with the
     raw maxima, the maxima over the pixels that have no alternative
     (plain_*: only rounding separates the results there), the number of
     pixels with alternatives, flagged and unresolved by the oracle, accepted
     through an alternative (rescued) and failed."""
     rgb = np.asarray(rgb, np.float64)
     depth = np.asarray(depth, np.float64)
-    alpha = ref.alpha if alpha is None else np.asarray(alpha, np.float64)
+    alpha = None if alpha is None else np.asarray(alpha, np.float64)
     ok, e_rgb, e_dep, e_alp = _pixel_errors(ref.rgb, ref.depth, ref.alpha, rgb, depth, alpha)
     H, W = ref.depth.shape
     flat_ok = ok.reshape(-1)
@@ -262,13 +266,14 @@ def compare(ref: Render, rgb, depth, alpha=None) -> dict:
         ends = np.searchsorted(ref.var_pix, bad, side="right")
         rgb_f = rgb.reshape(-1, 3)
         dep_f = depth.reshape(-1)
-        alp_f = alpha.reshape(-1)
+        alp_f = None if alpha is None else alpha.reshape(-1)
         for p, a, b in zip(bad, starts, ends):
             if a == b:
                 continue
             vv = ref.var_vals[a:b]
             okv, _, _, _ = _pixel_errors(vv[:, :3], vv[:, 3], vv[:, 4],
-                                         rgb_f[p][None, :], dep_f[p], alp_f[p])
+                                         rgb_f[p][None, :], dep_f[p],
+                                         None if alp_f is None else alp_f[p])
             if okv.any():
                 flat_ok[p] = True
                 rescued += 1

@@ -188,23 +188,35 @@ def _per_layer(vec):
 def test_adam_update_matches_oracle(gpu_renderer):
     """k_adam against the oracle's Adam on the same seeded FP32 gradients
     (three updates, changing learning rates): parameters, both moments and
-    the update count, to FP32 rounding."""
+    the update count, each element within the FP32 rounding bound of the
+    update's operations. The first moment is a sum of terms of either sign,
+    so its bound scales with the sum of their magnitudes (m_abs), not with
+    m; the parameter bound adds each step's update error (the quotient's
+    operations relative to m_abs) and the parameter's own rounding."""
     _, p0 = _random_params(40)
     gpu_renderer.up_set(p0)
     rng = np.random.default_rng(41)
+    u = 2.0 ** -24
     p, m, v = p0.astype(np.float64), np.zeros(p0.size), np.zeros(p0.size)
+    m_abs = np.zeros(p0.size)
+    tol_p = np.zeros(p0.size)
     for step, lr in enumerate((1e-3, 3e-3, 5e-4), start=1):
         g = (rng.normal(size=p0.size) * 10.0 ** rng.uniform(-4, 0, size=p0.size)).astype(np.float32)
         gpu_renderer.up_apply_grads(g, lr)
         p, m, v = U.adam_step(p, g.astype(np.float64), m, v, step, lr)
+        m_abs = U.ADAM_B1 * m_abs + (1.0 - U.ADAM_B1) * np.abs(g.astype(np.float64))
+        c1 = 1.0 / (1.0 - U.ADAM_B1 ** step)
+        den = np.sqrt(v / (1.0 - U.ADAM_B2 ** step)) + U.ADAM_EPS
+        tol_p += lr * c1 * m_abs * (16 * step * u) / den + 2 * u * np.abs(p)
     gp = gpu_renderer.up_get().astype(np.float64)
     gm, gv, gstep = gpu_renderer.up_state()
     assert gstep == 3
-    np.testing.assert_allclose(gm, m, rtol=2e-6, atol=0)
-    np.testing.assert_allclose(gv, v, rtol=2e-6, atol=0)
-    # per element: the parameter's own rounding plus the update's (lr scale)
-    np.testing.assert_allclose(gp, p, rtol=2e-7, atol=1e-5 * 5e-3)
-    print(f"adam: max |dp| {np.abs(gp - p).max():.2e}, max rel m {np.abs(gm / m - 1).max():.2e}")
+    dm, dv, dp = np.abs(gm - m), np.abs(gv - v), np.abs(gp - p)
+    print(f"adam: max |dm|/m_abs {np.max(dm / m_abs):.2e}, max |dv|/v {np.max(dv / v):.2e}, "
+          f"max |dp|/tol {np.max(dp / tol_p):.2f}")
+    assert np.all(dm <= 4 * 3 * u * m_abs)
+    assert np.all(dv <= 5 * 3 * u * v)
+    assert np.all(dp <= tol_p)
 
 
 def test_training_steps_match_oracle(gpu_renderer):
@@ -213,7 +225,7 @@ def test_training_steps_match_oracle(gpu_renderer):
     (bounded at relative L2 3e-2 per layer by the gradient test), so the
     first moments, linear in the gradients, are held to 3e-2 per layer and
     the second moments, quadratic, to 6e-2; the parameters (initial values
-    plus three updates) to 1e-3 over the vector, and the update direction of
+    plus three updates) to 1e-2 over the vector, and the update direction of
     every layer to a cosine of 0.97."""
     import torch
     params, p0 = _random_params(42)
@@ -234,7 +246,6 @@ def test_training_steps_match_oracle(gpu_renderer):
     gp = gpu_renderer.up_get().astype(np.float64)
     gm, gv, gstep = gpu_renderer.up_state()
     assert gstep == 3
-    assert _rel_l2(gp, p) < 1e-3
     for li, ((a_m, _), (b_m, _), (a_v, _), (b_v, _), (a_p, _), (b_p, _), (o_p, _)) in enumerate(
             zip(_per_layer(gm), _per_layer(m), _per_layer(gv), _per_layer(v), _per_layer(gp),
                 _per_layer(p), _per_layer(p0.astype(np.float64)))):
@@ -243,6 +254,11 @@ def test_training_steps_match_oracle(gpu_renderer):
         cos = float(du @ dr / (np.linalg.norm(du) * np.linalg.norm(dr)))
         print(f"layer {li + 1}: m rel L2 {em:.2e}, v rel L2 {ev:.2e}, update cosine {cos:.4f}")
         assert em < 3e-2 and ev < 6e-2 and cos > 0.97
+    # Adam's early updates are close to lr times the sign of the gradient, so
+    # an element whose gradient is within BF16 rounding of zero can step the
+    # other way: over the whole vector the parameters agree to 1e-2.
+    print(f"parameters: rel L2 {_rel_l2(gp, p):.2e}")
+    assert _rel_l2(gp, p) < 1e-2
 
 
 def test_learning_rate_schedule_matches_oracle(gpu_renderer):

@@ -187,6 +187,13 @@ def test_comparator_rescues_listed_alternatives():
     rep = oracle.compare(r, rgb, dep, alp)
     assert rep["failed"] == 0
     assert rep["rescued"] >= changed
+    # an image without an alpha channel is held to RGB and depth only: the
+    # alternatives still rescue it (their weights differ from the FP64 one)
+    rep = oracle.compare(r, rgb, dep)
+    assert rep["failed"] == 0 and rep["rescued"] >= changed
+    assert rep["max_abs_alpha"] == 0.0
+    rgb[np.unravel_index(int(r.var_pix[0]), r.depth.shape)] += 0.1
+    assert oracle.compare(r, rgb, dep)["failed"] == 1
 
 
 def test_two_saturated_alternative_is_listed():
