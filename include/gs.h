@@ -296,6 +296,24 @@ int gs_upsampler_load(gs_ctx *ctx, const char *path);
 int gs_upsampler_forward(gs_ctx *ctx, int32_t n, int32_t h, int32_t w, const float *rgb_lo,
                          const float *depth_lo, float *rgb_out, float *depth_out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * network forward as gs_upsampler_forward, with the same kernels and
+ * bitwise the same outputs, whose activations live in a fixed scratch array
+ * of 64 MiB that the library holds on every GPU it runs on until the
+ * process ends (208 bytes per low-resolution pixel: frames go through it as
+ * many at a time as fit, so n is unbounded). It calls no hipMalloc or
+ * hipFree and no allocating library routine.
+ *   Arguments as gs_upsampler_forward (all DEVICE, asynchronous on stream).
+ *   GS_ERR_INVALID_ARG if one frame's activations (208 h w bytes) exceed the
+ *   scratch array (h w > 322,630), GS_ERR_NOT_TRAINED before the weights
+ *   are set. Every call on one GPU shares that GPU's array and keeps the last
+ *   call's contents: calls that overlap on one GPU (different streams or
+ *   contexts without ordering between them) race and give wrong frames. */
+int gs_upsampler_forward_noalloc(gs_ctx *ctx, int32_t n, int32_t h, int32_t w,
+                                 const float *rgb_lo, const float *depth_lo, float *rgb_out,
+                                 float *depth_out, void *stream);
+
 /* Forward + backward for the loss mean_p sum_c w_c (pred_c - target_c)^2,
  * w = (1, 1, 1, 0.1) over (r, g, b, depth/10), targets rgb_hi [n][4h][4w][3]
  * and depth_hi [n][4h][4w] (DEVICE). Writes the loss and the gradient of the

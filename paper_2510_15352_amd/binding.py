@@ -29,7 +29,7 @@ EXPORTS = ("gs_abi_sizes", "gs_default_opts", "gs_create", "gs_destroy", "gs_las
            "gs_debug_project", "gs_autotune", "gs_set_instance_capacity", "gs_clear_graphs",
            "gs_upsampler_num_params", "gs_upsampler_init", "gs_upsampler_set_weights",
            "gs_upsampler_get_weights", "gs_upsampler_save", "gs_upsampler_load",
-           "gs_upsampler_forward", "gs_upsampler_grads", "gs_upsampler_step",
+           "gs_upsampler_forward", "gs_upsampler_forward_noalloc", "gs_upsampler_grads", "gs_upsampler_step",
            "gs_upsampler_apply_grads", "gs_upsampler_get_state", "gs_upsampler_lr",
            "gs_upsampler_score", "gs_upsampler_train", "gs_render_batch_upsampled", "gs_frame_psnr")
 
@@ -116,6 +116,7 @@ def load():
     L.gs_upsampler_save.argtypes = [vp, ctypes.c_char_p]
     L.gs_upsampler_load.argtypes = [vp, ctypes.c_char_p]
     L.gs_upsampler_forward.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
+    L.gs_upsampler_forward_noalloc.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
     L.gs_upsampler_grads.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp]
     L.gs_upsampler_step.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, fp, vp, vp]
     L.gs_upsampler_apply_grads.argtypes = [vp, vp, i64, fp]
@@ -378,6 +379,23 @@ class Renderer:
                                                   rgb.data_ptr(), depth.data_ptr(),
                                                   _stream_ptr(torch)))
         return rgb, depth
+
+    def up_forward_noalloc(self, rgb_lo, depth_lo, rgb_out, depth_out):
+        """gs_upsampler_forward_noalloc into caller-allocated outputs: every
+        tensor must already be a contiguous float32 tensor on the device of
+        the right size (nothing is allocated or copied here)."""
+        torch = self.torch
+        n, h, w, _ = rgb_lo.shape
+        shapes = ((rgb_lo, (n, h, w, 3)), (depth_lo, (n, h, w)), (rgb_out, (n, 4 * h, 4 * w, 3)),
+                  (depth_out, (n, 4 * h, 4 * w)))
+        for t, shp in shapes:
+            if not (torch.is_tensor(t) and t.device == self.device and t.dtype == torch.float32
+                    and t.is_contiguous() and tuple(t.shape) == shp):
+                raise ValueError(f"expected a contiguous float32 device tensor of shape {shp}")
+        self._check(self.lib.gs_upsampler_forward_noalloc(
+            self.ctx, n, h, w, rgb_lo.data_ptr(), depth_lo.data_ptr(), rgb_out.data_ptr(),
+            depth_out.data_ptr(), _stream_ptr(torch)))
+        return rgb_out, depth_out
 
     def up_grads(self, rgb_lo, depth_lo, rgb_hi, depth_hi):
         n, h, w, _ = rgb_lo.shape

@@ -149,6 +149,15 @@ struct Upsampler {
     DevBuf<float> lo_rgb, lo_depth, hi_rgb, hi_depth, intr_lo, score;
 };
 
+// Scratch of gs_upsampler_forward_noalloc: the FP32 four-channel input and
+// the three BF16 32-channel activations of as many frames as fit (208 bytes
+// per low-resolution pixel, each buffer 256-byte aligned). One copy per GPU
+// for the life of the process; host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr size_t kNoAllocBytesPerPixel = 4 * 4 + 3 * 32 * 2;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -161,6 +170,7 @@ struct GraphEntry {
 struct gs_ctx {
     int device = 0;
     int cu_count = 0;
+    unsigned char *scratch = nullptr;  // this device's copy of the scratch array
     std::string err;
     std::vector<std::unique_ptr<Scene>> scenes;
     DevBuf<SceneDev> d_scenes;
@@ -845,23 +855,34 @@ void up_alloc(gs_ctx *ctx, int n, int h, int w, bool train)
 // Network forward. With rgb / depth set (inference) the last layer's
 // epilogue is the head and writes the full-resolution frames; otherwise the
 // last layer writes y4 (FP32) for the training head.
+// Inference network on given buffers: x0f (n h w FP32 four-channel input)
+// -> a1 -> a2 -> a3 (BF16, 32 channels) -> the head, which writes the
+// full-resolution frames.
+void up_infer(gs_ctx *ctx, int n, int h, int w, hipStream_t st, const float *x0f, uint16_t *a1,
+              uint16_t *a2, uint16_t *a3, float *rgb, float *depth)
+{
+    Upsampler &U = ctx->up;
+    launch_up_conv(32, 32, UP_EPI_RELU_BF16_IN4, nullptr, U.wf[0].p, U.b[0].p, n, h, w, nullptr,
+                   a1, st, x0f);
+    launch_up_conv(32, 32, UP_EPI_RELU_BF16, a1, U.wf[1].p, U.b[1].p, n, h, w, nullptr, a2, st);
+    launch_up_conv(32, 32, UP_EPI_RELU_BF16, a2, U.wf[2].p, U.b[2].p, n, h, w, nullptr, a3, st);
+    launch_up_conv(32, 64, UP_EPI_HEAD, a3, U.wf[3].p, U.b[3].p, n, h, w, nullptr, nullptr, st,
+                   x0f, rgb, depth);
+}
+
 void up_forward(gs_ctx *ctx, int n, int h, int w, hipStream_t st, float *rgb = nullptr,
                 float *depth = nullptr)
 {
     Upsampler &U = ctx->up;
-    if (rgb)  // inference: the first layer reads x0f directly
-        launch_up_conv(32, 32, UP_EPI_RELU_BF16_IN4, nullptr, U.wf[0].p, U.b[0].p, n, h, w,
-                       nullptr, U.a1.p, st, U.x0f.p);
-    else
-        launch_up_conv(32, 32, UP_EPI_RELU_BF16, U.x0b.p, U.wf[0].p, U.b[0].p, n, h, w, nullptr,
-                       U.a1.p, st);
+    if (rgb) {  // inference: the first layer reads x0f directly
+        up_infer(ctx, n, h, w, st, U.x0f.p, U.a1.p, U.a2.p, U.a3.p, rgb, depth);
+        return;
+    }
+    launch_up_conv(32, 32, UP_EPI_RELU_BF16, U.x0b.p, U.wf[0].p, U.b[0].p, n, h, w, nullptr,
+                   U.a1.p, st);
     launch_up_conv(32, 32, UP_EPI_RELU_BF16, U.a1.p, U.wf[1].p, U.b[1].p, n, h, w, nullptr, U.a2.p, st);
     launch_up_conv(32, 32, UP_EPI_RELU_BF16, U.a2.p, U.wf[2].p, U.b[2].p, n, h, w, nullptr, U.a3.p, st);
-    if (rgb)
-        launch_up_conv(32, 64, UP_EPI_HEAD, U.a3.p, U.wf[3].p, U.b[3].p, n, h, w, nullptr,
-                       nullptr, st, U.x0f.p, rgb, depth);
-    else
-        launch_up_conv(32, 64, UP_EPI_F32, U.a3.p, U.wf[3].p, U.b[3].p, n, h, w, nullptr, U.y4.p, st);
+    launch_up_conv(32, 64, UP_EPI_F32, U.a3.p, U.wf[3].p, U.b[3].p, n, h, w, nullptr, U.y4.p, st);
 }
 
 // dy4 must be filled (training head); writes gw / gb of every layer.
@@ -998,6 +1019,9 @@ int gs_create(int hip_device, gs_ctx **out)
             HIP_CHECK(hipEventCreateWithFlags(&ctx->ev_join[l], hipEventDisableTiming));
         }
         HIP_CHECK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+        // the scratch array's address on this device (hip_device is current)
+        HIP_CHECK(hipGetSymbolAddress((void **)&ctx->scratch, HIP_SYMBOL(scratch)));
+        if (!ctx->scratch) throw GsError(GS_ERR_HIP, "no device address for the scratch array");
         return GS_OK;
     });
     if (rc != GS_OK) {
@@ -1653,6 +1677,52 @@ int gs_upsampler_forward(gs_ctx *ctx, int32_t n, int32_t h, int32_t w, const flo
             const int64_t lp = (int64_t)h * w, hp = lp * 16;
             launch_up_input(rgb_lo + c0 * lp * 3, depth_lo + c0 * lp, m * lp, U.x0f.p, nullptr, st);
             up_forward(ctx, m, h, w, st, rgb_out + c0 * hp * 3, depth_out + c0 * hp);
+        }
+        HIP_CHECK(hipGetLastError());
+        return GS_OK;
+    });
+}
+
+int gs_upsampler_forward_noalloc(gs_ctx *ctx, int32_t n, int32_t h, int32_t w,
+                                 const float *rgb_lo, const float *depth_lo, float *rgb_out,
+                                 float *depth_out, void *stream)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (n < 1 || h < 1 || w < 1 || !rgb_lo || !depth_lo || !rgb_out || !depth_out)
+        return fail(ctx, GS_ERR_INVALID_ARG, "bad upsampler forward arguments");
+    if (!ctx->up.ready) return fail(ctx, GS_ERR_NOT_TRAINED, "upsampler not initialised");
+    if (!ctx->scratch) return fail(ctx, GS_ERR_HIP, "scratch array has no device address");
+    // frames per pass: whole frames of activations in the scratch array
+    // (three alignment gaps of at most 255 bytes between the four buffers)
+    const uint64_t frame_bytes = (uint64_t)h * (uint64_t)w * kNoAllocBytesPerPixel;
+    const uint64_t fit = (kNoAllocScratchBytes - 3 * 256) / frame_bytes;
+    if (fit < 1)
+        return fail(ctx, GS_ERR_INVALID_ARG,
+                    "frame of " + std::to_string(w) + "x" + std::to_string(h) +
+                        " needs " + std::to_string(frame_bytes) +
+                        " bytes of activations, more than the " +
+                        std::to_string(kNoAllocScratchBytes) + "-byte scratch array");
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        hipStream_t st = (hipStream_t)stream;
+        if (!ctx->up.packed) up_pack(ctx, st);
+        const int per = (int)std::min<uint64_t>(fit, (uint64_t)kUpChunk);
+        const int64_t lp = (int64_t)h * w, hp = lp * 16;
+        auto align = [](size_t b) { return (b + 255) & ~size_t(255); };
+        for (int c0 = 0; c0 < n; c0 += per) {
+            const int m = std::min(per, n - c0);
+            const size_t px = (size_t)m * lp;
+            unsigned char *base = ctx->scratch;
+            float *x0f = reinterpret_cast<float *>(base);
+            uint16_t *act[3];
+            size_t off = align(px * 16);
+            for (int i = 0; i < 3; ++i) {
+                act[i] = reinterpret_cast<uint16_t *>(base + off);
+                off += align(px * 64);
+            }
+            launch_up_input(rgb_lo + c0 * lp * 3, depth_lo + c0 * lp, m * lp, x0f, nullptr, st);
+            up_infer(ctx, m, h, w, st, x0f, act[0], act[1], act[2], rgb_out + c0 * hp * 3,
+                     depth_out + c0 * hp);
         }
         HIP_CHECK(hipGetLastError());
         return GS_OK;
