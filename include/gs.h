@@ -171,6 +171,40 @@ int gs_render_batch(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const
                     const float *intrinsics, int32_t width, int32_t height, float *rgb,
                     float *depth, float *alpha, const gs_render_opts *opts, void *stream);
 
+/*
+ * Backward pass of the render (the splats of a scene are fitted by
+ * rendering them differentiably against images: Sec. 2.3, Sec. 3.1).
+ * Gradients of
+ *     L = sum over cameras and pixels of  grad_rgb . RGB + grad_depth * depth
+ *                                        + grad_alpha * alpha
+ * with respect to the parameters of scene `scene_id`, for n_cams cameras of
+ * that scene rendered as gs_render_batch renders them (same near plane and
+ * background from opts; NULL for defaults; opts->chunk_cams bounds the
+ * cameras per chunk). Every discrete decision of the forward pass (near
+ * plane, the 1/255 skip, the 1e-4 stop, the 0.99 clamp, the Jacobian's
+ * tangent clamp, the colour's clamp at 0) is held as the forward pass takes
+ * it, so this is the derivative of the branch the render follows.
+ *   poses, intrinsics  DEVICE float [n_cams][3][4], [n_cams][4]
+ *   grad_rgb           DEVICE float [n_cams][H][W][3] or NULL
+ *   grad_depth         DEVICE float [n_cams][H][W] or NULL (expected depth)
+ *   grad_alpha         DEVICE float [n_cams][H][W] or NULL (accumulated weight)
+ *                      (NULL gradients are zero; at least one is required)
+ *   d_means [N][3], d_scales [N][3], d_quats [N][4] (w, x, y, z, for the
+ *   quaternion as uploaded, not normalised), d_opacity [N],
+ *   d_sh [N][(deg+1)^2][3]: DEVICE float outputs in the order the scene was
+ *   uploaded in, overwritten (scales and opacities are the linear values the
+ *   scene was uploaded with).
+ * Every sum runs in a fixed order, so the result is deterministic. The call
+ * waits for `stream` (the instance buffers' overflow flag is read and the
+ * pass repeated with larger buffers when they overflowed).
+ * GS_ERR_INVALID_ARG for a bad scene id, size or null pointer.
+ */
+int gs_render_backward(gs_ctx *ctx, int32_t scene_id, int32_t n_cams, const float *poses,
+                       const float *intrinsics, int32_t width, int32_t height,
+                       const float *grad_rgb, const float *grad_depth, const float *grad_alpha,
+                       const gs_render_opts *opts, float *d_means, float *d_scales,
+                       float *d_quats, float *d_opacity, float *d_sh, void *stream);
+
 /* Camera-rate decimation (the paper renders at the camera's own frame rate,
  * below the control rate, Sec. 3.3; staggering the environments over the
  * period, so that every step renders a similar share, is this library's

@@ -24,7 +24,7 @@ GS_MODE_PLAIN, GS_MODE_BATCHED = 0, 1
 # every symbol include/gs.h declares
 EXPORTS = ("gs_abi_sizes", "gs_default_opts", "gs_create", "gs_destroy", "gs_last_error", "gs_upload_scene",
            "gs_release_scene", "gs_scene_size", "gs_render_batch", "gs_render_due",
-           "gs_render_batch_motion_blur", "gs_peak_probe",
+           "gs_render_batch_motion_blur", "gs_render_backward", "gs_peak_probe",
            "gs_last_stats",
            "gs_debug_project", "gs_autotune", "gs_set_instance_capacity", "gs_clear_graphs",
            "gs_upsampler_num_params", "gs_upsampler_init", "gs_upsampler_set_weights",
@@ -102,6 +102,8 @@ def load():
                                 ctypes.POINTER(RenderOpts), ctypes.POINTER(i32), vp]
     L.gs_render_batch_motion_blur.argtypes = [vp, i32, vp, vp, vp, vp, i32, i32, fp, i32, vp, vp,
                                               vp, ctypes.POINTER(RenderOpts), vp]
+    L.gs_render_backward.argtypes = [vp, i32, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp,
+                                     vp, vp, vp]
     L.gs_peak_probe.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
     L.gs_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.gs_debug_project.argtypes = [vp, i32, vp, vp, i32, i32, fp, vp]
@@ -204,6 +206,7 @@ class Renderer:
         d = SceneDesc(n, int(scene["sh_degree"]), kind, *ptrs)
         sid = ctypes.c_int32(-1)
         self._check(self.lib.gs_upload_scene(self.ctx, ctypes.byref(d), ctypes.byref(sid)))
+        self._keep[("deg", sid.value)] = int(scene["sh_degree"])
         return sid.value
 
     def release_scene(self, sid: int):
@@ -262,6 +265,43 @@ class Renderer:
             rgb.data_ptr(), depth.data_ptr(), al.data_ptr() if al is not None else None,
             ctypes.byref(o), _stream_ptr(torch)))
         return rgb, depth, al
+
+    def render_backward(self, scene_id, poses, intrinsics, width, height, grad_rgb=None,
+                        grad_depth=None, grad_alpha=None, opts=None, **kw):
+        """Gradients of sum(grad_rgb * rgb) + sum(grad_depth * depth) +
+        sum(grad_alpha * alpha) over the cameras' renders of one scene with
+        respect to its parameters; returns a dict of device tensors (means,
+        scales, quats, opacity, sh) in the scene's upload order."""
+        torch = self.torch
+        P, K = self._dev(poses), self._dev(intrinsics)
+        n = P.numel() // 12
+        if P.numel() != n * 12 or K.numel() != n * 4 or n < 1:
+            raise ValueError("poses must be [n,3,4] and intrinsics [n,4]")
+        ups = []
+        for t, last in ((grad_rgb, 3), (grad_depth, None), (grad_alpha, None)):
+            if t is None:
+                ups.append(None)
+                continue
+            t = self._dev(t)
+            want = n * height * width * (last or 1)
+            if t.numel() != want:
+                raise ValueError("upstream gradients must be [n,H,W,3] / [n,H,W]")
+            ups.append(t)
+        N = self.scene_size(scene_id)
+        nc = (self._keep[("deg", int(scene_id))] + 1) ** 2
+        dev = self.device
+        out = {"means": torch.empty((N, 3), dtype=torch.float32, device=dev),
+               "scales": torch.empty((N, 3), dtype=torch.float32, device=dev),
+               "quats": torch.empty((N, 4), dtype=torch.float32, device=dev),
+               "opacity": torch.empty((N,), dtype=torch.float32, device=dev),
+               "sh": torch.empty((N, nc, 3), dtype=torch.float32, device=dev)}
+        o = opts if opts is not None else self.opts(**kw)
+        self._check(self.lib.gs_render_backward(
+            self.ctx, int(scene_id), n, P.data_ptr(), K.data_ptr(), int(width), int(height),
+            *[u.data_ptr() if u is not None else None for u in ups], ctypes.byref(o),
+            out["means"].data_ptr(), out["scales"].data_ptr(), out["quats"].data_ptr(),
+            out["opacity"].data_ptr(), out["sh"].data_ptr(), _stream_ptr(torch)))
+        return out
 
     def render_motion_blur(self, scene_ids, poses, velocities, intrinsics, width, height,
                            shutter, n_sub, out=None, alpha=True, opts=None, **kw):

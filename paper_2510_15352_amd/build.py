@@ -13,8 +13,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgsmi.so")
-SOURCES = ["k_project.hip", "k_sort.hip", "k_raster.hip", "k_upsample.hip", "k_probe.hip",
-           "runtime.hip"]
+SOURCES = ["k_project.hip", "k_sort.hip", "k_raster.hip", "k_backward.hip", "k_upsample.hip",
+           "k_probe.hip", "runtime.hip"]
 ARCH = "gfx950"
 
 

@@ -16,7 +16,8 @@ __global__ void k_scene_prep(const float *__restrict__ means, const float *__res
                              const float *__restrict__ sh, int64_t n, int ncoef,
                              float4 *__restrict__ pos_op, float4 *__restrict__ m01,
                              float4 *__restrict__ m23, float2 *__restrict__ m8r,
-                             float *__restrict__ sh_planar, int *__restrict__ bad)
+                             float *__restrict__ sh_planar, float4 *__restrict__ quat,
+                             float4 *__restrict__ scale, int *__restrict__ bad)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
@@ -30,6 +31,8 @@ __global__ void k_scene_prep(const float *__restrict__ means, const float *__res
               o <= 1.0f && qn2 > 0.0f && isfinite(qn2);
     const float qi = rsqrtf(qn2);
     qw *= qi; qx *= qi; qy *= qi; qz *= qi;
+    if (quat) quat[g] = make_float4(qw, qx, qy, qz);
+    if (scale) scale[g] = make_float4(sx, sy, sz, qi);
     const float R00 = 1.0f - 2.0f * (qy * qy + qz * qz), R01 = 2.0f * (qx * qy - qw * qz),
                 R02 = 2.0f * (qx * qz + qw * qy);
     const float R10 = 2.0f * (qx * qy + qw * qz), R11 = 1.0f - 2.0f * (qx * qx + qz * qz),
@@ -191,13 +194,13 @@ __global__ void k_debug_project(SceneDev sc, const int32_t *__restrict__ perm,
 // ---------------------------------------------------------------- launch --
 void launch_scene_prep(const float *means, const float *scales, const float *quats,
                        const float *opacity, const float *sh, int64_t n, int ncoef, float4 *pos_op,
-                       float4 *m01, float4 *m23, float2 *m8r, float *sh_planar, int *bad,
-                       hipStream_t st)
+                       float4 *m01, float4 *m23, float2 *m8r, float *sh_planar, float4 *quat,
+                       float4 *scale, int *bad, hipStream_t st)
 {
     const int bs = 256;
     const int64_t grid = (n + bs - 1) / bs;
     hipLaunchKernelGGL(k_scene_prep, dim3((unsigned)grid), dim3(bs), 0, st, means, scales, quats,
-                       opacity, sh, n, ncoef, pos_op, m01, m23, m8r, sh_planar, bad);
+                       opacity, sh, n, ncoef, pos_op, m01, m23, m8r, sh_planar, quat, scale, bad);
 }
 
 void launch_camera_setup(const float *poses, const float *intr, const int32_t *cam_global,

@@ -48,6 +48,50 @@ struct RasterArgs {
     float blend_w;
 };
 
+// Backward pass (16x16 tiles: four 8x8 waves per tile; ten screen-space
+// gradient values per record: u, v, conic xx, xy, yy, opacity, r, g, b, z).
+constexpr int kBwdWaves = 4;
+constexpr int kBwdVals = 10;
+constexpr int kBwdBatch = 64;
+
+struct BwdArgs {
+    const uint2 *ranges;        // [n_cams * tiles_per_cam] into ivals
+    const uint32_t *ivals;      // tile-sorted instance values (record slots)
+    const float4 *rec;          // records by slot
+    const uint2 *rect;          // pixel boxes by slot
+    const uint32_t *inst_base;  // emission position of each slot's first instance
+    const int32_t *cam_global;  // chunk-local -> batch camera index
+    int tiles_x, tiles_per_cam, W, H;
+    float bg_r, bg_g, bg_b;
+    const float *g_rgb, *g_depth, *g_alpha;  // upstream gradients (nullable)
+    float *partial;             // [instance][wave][10]
+};
+
+struct BwdGaussArgs {
+    const float4 *pos_op, *m01, *m23;
+    const float2 *m8r;
+    const float *sh;            // planar [(deg+1)^2 * 3][n]
+    const float4 *quat;         // unit quaternion (w, x, y, z)
+    const float4 *scale;        // (sx, sy, sz, 1 / |q| as given)
+    const int32_t *perm;        // caller's index of each stored Gaussian
+    int64_t n;
+    const CamParams *cams;      // the chunk's cameras
+    const uint32_t *cam_slot;   // slot base of each chunk camera
+    const uint64_t *vis;        // visibility words by slot / 64
+    const float *rgrad;         // [slot][10]
+    int n_cams;
+    float *d_means, *d_scales, *d_quats, *d_opacity, *d_sh;  // caller order, added to
+};
+
+void launch_bwd_emission(const uint2 *srect, const uint32_t *dvals, const uint32_t *counts,
+                         uint32_t n_max, uint32_t *cnt, uint32_t *base, uint32_t *inst_base,
+                         float *partial, uint32_t cap, const ScanTemp &tmp, hipStream_t st);
+void launch_bwd_raster(const BwdArgs &a, int n_cams, hipStream_t st);
+void launch_bwd_record(const uint32_t *dvals, const uint32_t *base, const uint32_t *cnt,
+                       const uint32_t *counts, uint32_t n_max, const float *partial, float *rgrad,
+                       hipStream_t st);
+void launch_bwd_gauss(int deg, const BwdGaussArgs &a, hipStream_t st);
+
 // Sub-frame camera poses of a motion-blurred frame: for every camera i and
 // sub-frame k < K, the pose with centre C_i - v_i * offs[k] (rotation kept),
 // written as out[k][i][3][4].
@@ -58,10 +102,12 @@ void launch_blur_poses(const float *poses, const float *vel, int n_cams, const f
 void launch_blur_finalize(float *depth, float *alpha_sum, float *alpha_out, int64_t n_px,
                           float inv_k, hipStream_t st);
 
+// quat / scale (nullable): the unit quaternion and (scales, 1 / |q|) kept
+// for the backward pass.
 void launch_scene_prep(const float *means, const float *scales, const float *quats,
                        const float *opacity, const float *sh, int64_t n, int ncoef, float4 *pos_op,
-                       float4 *m01, float4 *m23, float2 *m8r, float *sh_planar, int *bad,
-                       hipStream_t st);
+                       float4 *m01, float4 *m23, float2 *m8r, float *sh_planar, float4 *quat,
+                       float4 *scale, int *bad, hipStream_t st);
 void launch_camera_setup(const float *poses, const float *intr, const int32_t *cam_global,
                          int n_cams, int W, int H, CamParams *out, hipStream_t st);
 void launch_project(int deg, const ProjItem *items, int n_items, const SceneDev *scenes,

@@ -69,6 +69,7 @@ struct Scene {
     DevBuf<float4> pos_op, m01, m23;
     DevBuf<float2> m8r;
     DevBuf<float> sh;
+    DevBuf<float4> quat, scale;  // unit quaternion, (scales, 1/|q|): read by the backward pass
     int graph_refs = 0;
 };
 
@@ -198,6 +199,10 @@ struct gs_ctx {
     hipEvent_t ev_fork = nullptr, ev_join[kLanes - 1] = {};
 
     Upsampler up;
+    // backward pass: per-record tile counts, their scan, emission base by
+    // slot, screen-space record gradients, per (instance, wave) partial sums
+    DevBuf<uint32_t> bw_cnt, bw_base, bw_inst_base;
+    DevBuf<float> bw_rgrad, bw_partial;
     std::vector<hipEvent_t> events;  // pool for stage timing
     std::map<std::string, std::unique_ptr<GraphEntry>> graphs;
     std::map<std::string, Choice> tuned;
@@ -445,6 +450,63 @@ struct StageTimer {
     }
 };
 
+// Projection, compaction, depth sort, tile emission, tile sort and ranges
+// of one chunk on lane L (stream s); returns which half of the instance
+// ping-pong holds the tile-sorted instances (the depth-sorted records are
+// in L.dvals[depth_half] when depth_half is given).
+int enqueue_chunk_bins(gs_ctx *ctx, const Plan &P, const Chunk &c, Lane &L, hipStream_t s,
+                       float near, uint32_t cap, StageTimer &T, int *depth_half = nullptr)
+{
+    const Choice &ch = P.ch;
+    size_t t0;
+    ScanTemp scan{L.scan_partial.p};
+    SegSortTemp sort{L.sort_hist.p, L.sort_tp.p, L.sort_len.p, scan};
+    const CamParams *cams = ctx->cams.p + c.start;
+    const uint32_t *cam_slot = P.d_cam_slot.p + c.start;
+    const uint32_t n_words = (uint32_t)(c.slots / 64);
+    t0 = T.begin();
+    for (int d = 0; d < 4; ++d)
+        if (c.item_cnt[d])
+            launch_project(d, P.d_items.p + c.item_off[d], c.item_cnt[d], ctx->d_scenes.p, cams,
+                           cam_slot, near, P.W, P.H, L.rec.p, L.rect.p,
+                           L.zbits.p, L.vis.p, s);
+    T.end(GS_STAGE_PROJECT, t0);
+    // visible count, order-preserving compaction, per-camera segments
+    t0 = T.begin();
+    compact_visible(L.vis.p, n_words, cam_slot, c.count, L.zbits.p, L.dkeys[0].p,
+                    L.dvals[0].p, L.counts.p + 0, L.vis_start.p, scan, s);
+    T.end(GS_STAGE_COMPACT, t0);
+    // depth sort inside each camera's segment: key = z bits (z > 0)
+    t0 = T.begin();
+    const int r = seg_sort_u32(L.dkeys[0].p, L.dvals[0].p, L.dkeys[1].p, L.dvals[1].p,
+                               L.vis_start.p, c.count, (uint32_t)c.slots, 31, 0u, sort, s,
+                               L.rect.p, L.srect.p);
+    T.end(GS_STAGE_DEPTH_SORT, t0);
+    // tile instances in (camera, depth, index) order, keyed by tile
+    t0 = T.begin();
+    emit_instances(L.dvals[r].p, L.counts.p + 0, (uint32_t)c.slots, L.vis_start.p, c.count,
+                   L.srect.p, ch.tw, ch.th, P.tiles_x, cap, L.ikeys[0].p, L.ivals[0].p,
+                   L.inst_start.p, L.counts.p, L.flags.p, scan, s);
+    T.end(GS_STAGE_EMIT, t0);
+    // stable sort by tile inside each camera keeps the depth order in
+    // each tile
+    const uint64_t n_tiles = (uint64_t)c.count * P.tiles_per_cam;
+    const int tbits = std::max(1, bits_for((uint64_t)P.tiles_per_cam));
+    // radix passes inside each camera's segment, the last one turning
+    // the keys into camera * tiles + tile, then the ranges
+    t0 = T.begin();
+    const int r2 = seg_sort_u32(L.ikeys[0].p, L.ivals[0].p, L.ikeys[1].p, L.ivals[1].p,
+                                L.inst_start.p, c.count, cap, tbits, (uint32_t)P.tiles_per_cam,
+                                sort, s);
+    T.end(GS_STAGE_TILE_SORT, t0);
+    t0 = T.begin();
+    launch_zero_u32((uint32_t *)L.ranges.p, n_tiles * 2, s);
+    launch_ranges(L.ikeys[r2].p, L.counts.p + 2, L.ranges.p, cap, s);
+    T.end(GS_STAGE_RANGES, t0);
+    if (depth_half) *depth_half = r;
+    return r2;
+}
+
 // Enqueue the whole render of a plan on `st` (also used under capture).
 // With several lanes, chunk ci runs on lane ci mod n_lanes: lane 0 on `st`,
 // lane l > 0 on aux[l - 1], forked from `st` after the camera setup and
@@ -477,50 +539,7 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
         const int lane = (int)(ci % (size_t)n_lanes);
         const hipStream_t s = lane ? aux[lane - 1] : st;
         T.st = s;
-        ScanTemp scan{L.scan_partial.p};
-        SegSortTemp sort{L.sort_hist.p, L.sort_tp.p, L.sort_len.p, scan};
-        const CamParams *cams = ctx->cams.p + c.start;
-        const uint32_t *cam_slot = P.d_cam_slot.p + c.start;
-        const uint32_t n_words = (uint32_t)(c.slots / 64);
-        t0 = T.begin();
-        for (int d = 0; d < 4; ++d)
-            if (c.item_cnt[d])
-                launch_project(d, P.d_items.p + c.item_off[d], c.item_cnt[d], ctx->d_scenes.p, cams,
-                               cam_slot, near, P.W, P.H, L.rec.p, L.rect.p,
-                               L.zbits.p, L.vis.p, s);
-        T.end(GS_STAGE_PROJECT, t0);
-        // visible count, order-preserving compaction, per-camera segments
-        t0 = T.begin();
-        compact_visible(L.vis.p, n_words, cam_slot, c.count, L.zbits.p, L.dkeys[0].p,
-                        L.dvals[0].p, L.counts.p + 0, L.vis_start.p, scan, s);
-        T.end(GS_STAGE_COMPACT, t0);
-        // depth sort inside each camera's segment: key = z bits (z > 0)
-        t0 = T.begin();
-        const int r = seg_sort_u32(L.dkeys[0].p, L.dvals[0].p, L.dkeys[1].p, L.dvals[1].p,
-                                   L.vis_start.p, c.count, (uint32_t)c.slots, 31, 0u, sort, s,
-                                   L.rect.p, L.srect.p);
-        T.end(GS_STAGE_DEPTH_SORT, t0);
-        // tile instances in (camera, depth, index) order, keyed by tile
-        t0 = T.begin();
-        emit_instances(L.dvals[r].p, L.counts.p + 0, (uint32_t)c.slots, L.vis_start.p, c.count,
-                       L.srect.p, ch.tw, ch.th, P.tiles_x, cap, L.ikeys[0].p, L.ivals[0].p,
-                       L.inst_start.p, L.counts.p, L.flags.p, scan, s);
-        T.end(GS_STAGE_EMIT, t0);
-        // stable sort by tile inside each camera keeps the depth order in
-        // each tile
-        const uint64_t n_tiles = (uint64_t)c.count * P.tiles_per_cam;
-        const int tbits = std::max(1, bits_for((uint64_t)P.tiles_per_cam));
-        // radix passes inside each camera's segment, the last one turning
-        // the keys into camera * tiles + tile, then the ranges
-        t0 = T.begin();
-        const int r2 = seg_sort_u32(L.ikeys[0].p, L.ivals[0].p, L.ikeys[1].p, L.ivals[1].p,
-                                    L.inst_start.p, c.count, cap, tbits, (uint32_t)P.tiles_per_cam,
-                                    sort, s);
-        T.end(GS_STAGE_TILE_SORT, t0);
-        t0 = T.begin();
-        launch_zero_u32((uint32_t *)L.ranges.p, n_tiles * 2, s);
-        launch_ranges(L.ikeys[r2].p, L.counts.p + 2, L.ranges.p, cap, s);
-        T.end(GS_STAGE_RANGES, t0);
+        const int r2 = enqueue_chunk_bins(ctx, P, c, L, s, near, cap, T);
         RasterArgs a;
         a.ranges = L.ranges.p;
         a.ivals = L.ivals[r2].p;
@@ -723,6 +742,122 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
     ctx->last.lds_batch = ch.batch;
     ctx->last.chunk_cams = ch.chunk;
     ctx->last.persistent = ch.persistent;
+    return GS_OK;
+}
+
+// Backward pass of the render of n_cams cameras of one scene: the forward
+// binning of every chunk, then the gradient kernels (k_backward.hip), all on
+// one stream so that the per-Gaussian sums are added chunk after chunk.
+int render_backward_impl(gs_ctx *ctx, int32_t scene_id, int32_t n_cams, const float *poses,
+                         const float *intr, int32_t W, int32_t H, const float *g_rgb,
+                         const float *g_depth, const float *g_alpha, const gs_render_opts &o,
+                         float *d_means, float *d_scales, float *d_quats, float *d_opacity,
+                         float *d_sh, hipStream_t st)
+{
+    Scene &sc = *ctx->scenes[scene_id];
+    const int nc = (sc.deg + 1) * (sc.deg + 1);
+    std::vector<int32_t> ids((size_t)n_cams, scene_id);
+    Choice ch;
+    ch.tw = 16;
+    ch.th = 16;
+    ch.batch = kBwdBatch;
+    ch.chunk = o.chunk_cams > 0 ? std::min(o.chunk_cams, kMaxChunkCams) : 512;
+    ch.persistent = 0;
+    sync_scene_table(ctx);
+    ctx->last = gs_stats{};
+    int regrows = 0;
+    for (int attempt = 0; attempt < 6; ++attempt) {
+        std::unique_ptr<Plan> P = make_plan(ctx, n_cams, ids.data(), W, H, ch);
+        if (ensure_workspace(ctx, *P, 1)) clear_graphs(ctx);
+        const uint64_t slots = std::max<uint64_t>(P->max_slots, 64);
+        ctx->bw_cnt.reserve(slots);
+        ctx->bw_base.reserve(slots);
+        ctx->bw_inst_base.reserve(slots);
+        ctx->bw_rgrad.reserve(slots * kBwdVals);
+        ctx->bw_partial.reserve(ctx->inst_cap * kBwdWaves * kBwdVals);
+        const uint32_t cap = (uint32_t)ctx->inst_cap;
+        const int64_t n = sc.n;
+        launch_zero_u32(reinterpret_cast<uint32_t *>(d_means), (uint64_t)n * 3, st);
+        launch_zero_u32(reinterpret_cast<uint32_t *>(d_scales), (uint64_t)n * 3, st);
+        launch_zero_u32(reinterpret_cast<uint32_t *>(d_quats), (uint64_t)n * 4, st);
+        launch_zero_u32(reinterpret_cast<uint32_t *>(d_opacity), (uint64_t)n, st);
+        launch_zero_u32(reinterpret_cast<uint32_t *>(d_sh), (uint64_t)n * nc * 3, st);
+        Lane &L = ctx->lanes[0];
+        launch_zero_u32(reinterpret_cast<uint32_t *>(L.flags.p), sizeof(DevFlags) / 4, st);
+        launch_camera_setup(poses, intr, P->d_order.p, P->n_cams, W, H, ctx->cams.p, st);
+        StageTimer off{ctx, st, false};
+        for (const Chunk &c : P->chunks) {
+            int r = 0;
+            const int r2 = enqueue_chunk_bins(ctx, *P, c, L, st, o.near_plane, cap, off, &r);
+            ScanTemp scan{L.scan_partial.p};
+            launch_bwd_emission(L.srect.p, L.dvals[r].p, L.counts.p, (uint32_t)c.slots,
+                                ctx->bw_cnt.p, ctx->bw_base.p, ctx->bw_inst_base.p,
+                                ctx->bw_partial.p, cap, scan, st);
+            BwdArgs a;
+            a.ranges = L.ranges.p;
+            a.ivals = L.ivals[r2].p;
+            a.rec = L.rec.p;
+            a.rect = L.rect.p;
+            a.inst_base = ctx->bw_inst_base.p;
+            a.cam_global = P->d_order.p + c.start;
+            a.tiles_x = P->tiles_x;
+            a.tiles_per_cam = P->tiles_per_cam;
+            a.W = W;
+            a.H = H;
+            a.bg_r = o.bg[0];
+            a.bg_g = o.bg[1];
+            a.bg_b = o.bg[2];
+            a.g_rgb = g_rgb;
+            a.g_depth = g_depth;
+            a.g_alpha = g_alpha;
+            a.partial = ctx->bw_partial.p;
+            launch_bwd_raster(a, c.count, st);
+            launch_bwd_record(L.dvals[r].p, ctx->bw_base.p, ctx->bw_cnt.p, L.counts.p,
+                              (uint32_t)c.slots, ctx->bw_partial.p, ctx->bw_rgrad.p, st);
+            BwdGaussArgs b;
+            b.pos_op = sc.pos_op.p;
+            b.m01 = sc.m01.p;
+            b.m23 = sc.m23.p;
+            b.m8r = sc.m8r.p;
+            b.sh = sc.sh.p;
+            b.quat = sc.quat.p;
+            b.scale = sc.scale.p;
+            b.perm = sc.perm.p;
+            b.n = n;
+            b.cams = ctx->cams.p + c.start;
+            b.cam_slot = P->d_cam_slot.p + c.start;
+            b.vis = L.vis.p;
+            b.rgrad = ctx->bw_rgrad.p;
+            b.n_cams = c.count;
+            b.d_means = d_means;
+            b.d_scales = d_scales;
+            b.d_quats = d_quats;
+            b.d_opacity = d_opacity;
+            b.d_sh = d_sh;
+            launch_bwd_gauss(sc.deg, b, st);
+        }
+        HIP_CHECK(hipGetLastError());
+        DevFlags f;
+        read_flags(ctx, 1, st, f);
+        ctx->last.visible = (int64_t)f.visible;
+        ctx->last.instances = (int64_t)f.instances;
+        if (!f.overflow) break;
+        ++regrows;
+        uint64_t want = std::max<uint64_t>((uint64_t)f.max_inst + f.max_inst / 4 + 1024,
+                                           ctx->inst_cap * 2);
+        if (want > kMaxInstCap) want = kMaxInstCap;
+        if (want <= ctx->inst_cap)
+            return fail(ctx, GS_ERR_CAPACITY, "instance count per chunk exceeds 2^31");
+        ctx->inst_cap = want;
+        clear_graphs(ctx);
+        if (attempt == 5) return fail(ctx, GS_ERR_CAPACITY, "instance buffers kept overflowing");
+    }
+    ctx->last.instance_capacity = (int64_t)ctx->inst_cap;
+    ctx->last.regrows = regrows;
+    ctx->last.tile_w = ch.tw;
+    ctx->last.tile_h = ch.th;
+    ctx->last.lds_batch = ch.batch;
+    ctx->last.chunk_cams = ch.chunk;
     return GS_OK;
 }
 
@@ -1081,6 +1216,8 @@ int gs_upload_scene(gs_ctx *ctx, const gs_scene_desc *d, int32_t *scene_id_out)
         s->m23.reserve(n);
         s->m8r.reserve(n);
         s->sh.reserve((size_t)n * nc * 3);
+        s->quat.reserve(n);
+        s->scale.reserve(n);
         DevBuf<float> tmp;
         DevBuf<int> bad;
         bad.reserve(1);
@@ -1151,7 +1288,7 @@ int gs_upload_scene(gs_ctx *ctx, const gs_scene_desc *d, int32_t *scene_id_out)
         const float *m = tmp.p + off[0], *sc = tmp.p + off[1], *q = tmp.p + off[2],
                     *op = tmp.p + off[3], *sh = tmp.p + off[4];
         launch_scene_prep(m, sc, q, op, sh, n, nc, s->pos_op.p, s->m01.p, s->m23.p, s->m8r.p,
-                          s->sh.p, bad.p, nullptr);
+                          s->sh.p, s->quat.p, s->scale.p, bad.p, nullptr);
         HIP_CHECK(hipGetLastError());
         int hbad = 0;
         HIP_CHECK(hipMemcpy(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost));
@@ -1217,6 +1354,35 @@ int gs_render_batch(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const
         HIP_CHECK(hipSetDevice(ctx->device));
         return render_impl(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb, depth,
                            alpha, o, (hipStream_t)stream, nullptr);
+    });
+}
+
+int gs_render_backward(gs_ctx *ctx, int32_t scene_id, int32_t n_cams, const float *poses,
+                       const float *intrinsics, int32_t width, int32_t height,
+                       const float *grad_rgb, const float *grad_depth, const float *grad_alpha,
+                       const gs_render_opts *opts, float *d_means, float *d_scales,
+                       float *d_quats, float *d_opacity, float *d_sh, void *stream)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    if (scene_id < 0 || scene_id >= (int)ctx->scenes.size() || !ctx->scenes[scene_id])
+        return fail(ctx, GS_ERR_INVALID_ARG, "no such scene");
+    if (n_cams < 1) return fail(ctx, GS_ERR_INVALID_ARG, "n_cams must be >= 1");
+    if (!poses || !intrinsics)
+        return fail(ctx, GS_ERR_INVALID_ARG, "null poses/intrinsics");
+    if (!grad_rgb && !grad_depth && !grad_alpha)
+        return fail(ctx, GS_ERR_INVALID_ARG, "no upstream gradient given");
+    if (!d_means || !d_scales || !d_quats || !d_opacity || !d_sh)
+        return fail(ctx, GS_ERR_INVALID_ARG, "null gradient output");
+    if (width < 1 || height < 1 || width > 65535 || height > 65535)
+        return fail(ctx, GS_ERR_INVALID_ARG, "width/height must be in [1, 65535]");
+    gs_render_opts o;
+    gs_default_opts(&o);
+    if (opts) o = *opts;
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        return render_backward_impl(ctx, scene_id, n_cams, poses, intrinsics, width, height,
+                                    grad_rgb, grad_depth, grad_alpha, o, d_means, d_scales,
+                                    d_quats, d_opacity, d_sh, (hipStream_t)stream);
     });
 }
 
