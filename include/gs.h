@@ -93,7 +93,9 @@ typedef struct {
     int32_t streams;   /* BATCHED: chunk pipelines, each on its own stream (1..4; 0 =
                           4): the raster of one chunk overlaps the next chunks'
                           projection and sorts (timing renders always use one) */
-    int32_t reserved[2];
+    int32_t sync;      /* gs_render_batch: 1 = return only when the render has finished
+                          (see gs_render_batch); 0 (default) = asynchronous */
+    int32_t reserved[1];
 } gs_render_opts;
 
 /* Stages timed when gs_render_opts.timing is set (indices of stage_ms). */
@@ -123,6 +125,14 @@ typedef struct {
     int64_t pairs_issued;    /* lanes the raster's walk issued: 64 per (wave, record) step,
                                 live pixels or not (count_pairs renders) */
 } gs_stats;
+
+/* Status of the context's renders. wait != 0: first wait for the last render
+ * enqueued (gs_render_batch and the other render calls). Returns
+ * GS_ERR_CAPACITY when a render that returned without waiting overflowed
+ * the instance buffers since the last call (its frames are incomplete; the
+ * buffers have been grown, so rendering again gives complete frames),
+ * GS_ERR_HIP when the device reported an error, GS_OK otherwise. */
+int gs_render_status(gs_ctx *ctx, int32_t wait);
 
 /* sizeof of gs_scene_desc, gs_render_opts and gs_stats as compiled into the
  * library (lets bindings check their struct layouts). Returns GS_OK. */
@@ -160,12 +170,20 @@ int64_t gs_scene_size(gs_ctx *ctx, int32_t scene_id);
  *   rgb, depth  DEVICE float outputs (layouts in the header comment)
  *   alpha       DEVICE float [n_cams][H][W] or NULL
  *   opts        NULL for defaults
- * Work is enqueued on `stream`; the call then waits for that stream to read
- * the device overflow flag of the instance buffers, regrows them and renders
- * again if they overflowed, so outputs are complete when it returns GS_OK.
- * In BATCHED mode with use_graph the first call for a given configuration
- * (cameras, scenes, sizes, options, pointers) captures a HIP graph and later
- * calls replay it.
+ * Asynchronous on `stream`: the call enqueues the render and returns; the
+ * outputs are valid once the stream has reached that point. The instance
+ * buffers (tile entries of a camera chunk) are sized by the renders
+ * themselves: the first render of a configuration (cameras, scenes, sizes,
+ * choice, pipelines), and every render with opts->sync, timing or
+ * count_pairs set, waits for the stream, grows the buffers and renders again
+ * if they overflowed, so it returns complete outputs. Later renders of the
+ * configuration do not wait: each call first looks, without waiting, at the
+ * renders that have finished, and grows the buffers when a chunk came
+ * within a fifth of their size; if a render overflowed anyway its frames are
+ * incomplete and gs_render_status reports it (GS_ERR_CAPACITY, the buffers
+ * already grown). In BATCHED mode with use_graph the first call for a given
+ * configuration and set of buffers captures a HIP graph and later calls
+ * replay it with no host synchronisation.
  */
 int gs_render_batch(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const float *poses,
                     const float *intrinsics, int32_t width, int32_t height, float *rgb,

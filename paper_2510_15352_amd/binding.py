@@ -25,7 +25,7 @@ GS_MODE_PLAIN, GS_MODE_BATCHED = 0, 1
 EXPORTS = ("gs_abi_sizes", "gs_default_opts", "gs_create", "gs_destroy", "gs_last_error", "gs_upload_scene",
            "gs_release_scene", "gs_scene_size", "gs_render_batch", "gs_render_due",
            "gs_render_batch_motion_blur", "gs_render_backward", "gs_peak_probe",
-           "gs_last_stats",
+           "gs_last_stats", "gs_render_status",
            "gs_debug_project", "gs_autotune", "gs_set_instance_capacity", "gs_clear_graphs",
            "gs_upsampler_num_params", "gs_upsampler_init", "gs_upsampler_set_weights",
            "gs_upsampler_get_weights", "gs_upsampler_save", "gs_upsampler_load",
@@ -52,7 +52,8 @@ class RenderOpts(ctypes.Structure):
                 ("lds_batch", ctypes.c_int32), ("chunk_cams", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("count_pairs", ctypes.c_int32),
-                ("streams", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("streams", ctypes.c_int32), ("sync", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 class TrainOpts(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int32), ("steps", ctypes.c_int32), ("lr", ctypes.c_float),
@@ -106,6 +107,7 @@ def load():
                                      vp, vp, vp]
     L.gs_peak_probe.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
     L.gs_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.gs_render_status.argtypes = [vp, i32]
     L.gs_debug_project.argtypes = [vp, i32, vp, vp, i32, i32, fp, vp]
     L.gs_autotune.argtypes = [vp, i32, vp, vp, vp, i32, i32, vp, vp, ctypes.c_char_p, vp]
     L.gs_set_instance_capacity.argtypes = [vp, i64]
@@ -218,7 +220,7 @@ class Renderer:
     # ------------------------------------------------------------ render --
     def opts(self, mode="batched", tile=None, lds_batch=0, chunk_cams=0, persistent=-1,
              use_graph=False, near=0.2, bg=(0.0, 0.0, 0.0), timing=False, count_pairs=False,
-             streams=0):
+             streams=0, sync=False):
         o = RenderOpts()
         self.lib.gs_default_opts(ctypes.byref(o))
         o.mode = GS_MODE_PLAIN if mode == "plain" else GS_MODE_BATCHED
@@ -231,6 +233,7 @@ class Renderer:
         o.timing = int(bool(timing))
         o.count_pairs = int(bool(count_pairs))
         o.streams = int(streams)
+        o.sync = int(bool(sync))
         o.near_plane = float(near)
         for i in range(3):
             o.bg[i] = float(bg[i])
@@ -353,6 +356,11 @@ class Renderer:
             rgb.data_ptr(), depth.data_ptr(), al.data_ptr() if al is not None else None,
             ctypes.byref(o), ctypes.byref(nd), _stream_ptr(torch)))
         return nd.value
+
+    def status(self, wait: bool = True):
+        """gs_render_status: raises GsError (GS_ERR_CAPACITY) when a render
+        that returned without waiting overflowed its instance buffers."""
+        self._check(self.lib.gs_render_status(self.ctx, int(bool(wait))))
 
     def peak_probe(self, kind: int) -> float:
         """Measured rate: 0 FMA lane-ops/s, 1 v_exp_f32 lane-ops/s, 2 copy bytes/s."""

@@ -22,6 +22,17 @@ struct RenderFlags {
     unsigned long long pairs_issued;
 };
 
+// What the device reports about finished renders, in mapped host memory:
+// monotonic counts (never reset, so a render finishing while the host reads
+// cannot undo an earlier report) and the counts of the last finished render.
+struct RenderStatus {
+    unsigned long long renders;    // renders finished
+    unsigned long long overflows;  // of which overflowed an instance buffer
+    unsigned long long max_inst;   // largest instance count of one chunk seen
+    unsigned long long pad;
+    RenderFlags last;              // the last finished render (all its lanes)
+};
+
 struct ScanTemp {
     uint32_t *partial;  // >= 4096 entries
 };

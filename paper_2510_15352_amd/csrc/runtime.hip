@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -119,6 +120,38 @@ struct Lane {
 
 constexpr int kLanes = 4;  // chunk pipelines, one stream each
 
+struct LaneFlagPtrs {
+    const RenderFlags *p[kLanes];
+};
+
+// End of a render (one thread): the render's counts over its lanes, folded
+// into the monotonic device status, which is then written to the host's
+// mapped copy (the host reads it after the render's event, or without
+// waiting to look at renders that have finished).
+__global__ void k_status_merge(LaneFlagPtrs lanes, int n_lanes, RenderStatus *dev,
+                               RenderStatus *host)
+{
+    RenderFlags f{};
+    for (int l = 0; l < n_lanes; ++l) {
+        const RenderFlags &x = *lanes.p[l];
+        f.overflow |= x.overflow;
+        f.max_inst = max(f.max_inst, x.max_inst);
+        f.visible += x.visible;
+        f.instances += x.instances;
+        f.pairs_contrib += x.pairs_contrib;
+        f.pairs_eval += x.pairs_eval;
+        f.pairs_issued += x.pairs_issued;
+    }
+    RenderStatus s = *dev;
+    s.renders += 1;
+    s.overflows += f.overflow ? 1ull : 0ull;
+    if ((unsigned long long)f.max_inst > s.max_inst) s.max_inst = f.max_inst;
+    s.last = f;
+    *dev = s;
+    *host = s;
+    __threadfence_system();
+}
+
 // How the raster stores a frame: as the frame itself, or as sub-frame k of a
 // blended (motion-blurred) frame (mode 1 for the first, 2 for the others).
 struct Blend {
@@ -191,7 +224,18 @@ struct gs_ctx {
     // 16 B) take at most a third of the device memory.
     uint64_t slot_budget = uint64_t(1) << 27;
 
-    DevFlags *host_flags = nullptr;  // pinned, one per lane
+    // device status of finished renders and its mapped host copy
+    RenderStatus *status_host = nullptr;
+    RenderStatus *status_host_dev = nullptr;  // device address of status_host
+    DevBuf<RenderStatus> status_dev;
+    unsigned long long acked_overflows = 0;   // overflows already acted on
+    hipEvent_t ev_done = nullptr;             // recorded after every render
+    bool pending = false;                     // an asynchronous render may still run
+    bool last_deferred = false;               // the last render returned before finishing
+    int capacity_errors = 0;                  // overflowed renders not yet reported
+    // configurations (cameras, scenes, size, choice, pipelines) rendered once
+    // with a wait, which sized the instance buffers for them
+    std::set<std::string> sized;
     hipStream_t capture_stream = nullptr;
     // streams of the lanes after the first, for captured and eager renders
     hipStream_t capture_aux[kLanes - 1] = {};
@@ -450,6 +494,18 @@ struct StageTimer {
     }
 };
 
+void clear_graphs(gs_ctx *ctx);
+
+// End of a render on `st` (after the join): fold the lanes' flags into the
+// status block and record the render's event. Also used under capture.
+void enqueue_status(gs_ctx *ctx, int n_lanes, hipStream_t st)
+{
+    LaneFlagPtrs lp{};
+    for (int l = 0; l < n_lanes && l < kLanes; ++l) lp.p[l] = ctx->lanes[l].flags.p;
+    hipLaunchKernelGGL(k_status_merge, dim3(1), dim3(1), 0, st, lp, std::min(n_lanes, kLanes),
+                       ctx->status_dev.p, ctx->status_host_dev);
+}
+
 // Projection, compaction, depth sort, tile emission, tile sort and ranges
 // of one chunk on lane L (stream s); returns which half of the instance
 // ping-pong holds the tile-sorted instances (the depth-sorted records are
@@ -566,27 +622,58 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
         HIP_CHECK(hipEventRecord(ctx->ev_join[l - 1], aux[l - 1]));
         HIP_CHECK(hipStreamWaitEvent(st, ctx->ev_join[l - 1], 0));
     }
+    enqueue_status(ctx, n_lanes, st);
     HIP_CHECK(hipGetLastError());
 }
 
-// Copy every lane's flags to the pinned host block on `st` (after the join).
-void read_flags(gs_ctx *ctx, int n_lanes, hipStream_t st, DevFlags &out)
+// Wait for the last render and return its counts.
+void wait_status(gs_ctx *ctx, DevFlags &out)
 {
-    for (int l = 0; l < n_lanes; ++l)
-        HIP_CHECK(hipMemcpyAsync(ctx->host_flags + l, ctx->lanes[l].flags.p, sizeof(DevFlags),
-                                 hipMemcpyDeviceToHost, st));
-    HIP_CHECK(hipStreamSynchronize(st));
-    out = DevFlags{};
-    for (int l = 0; l < n_lanes; ++l) {
-        const DevFlags &f = ctx->host_flags[l];
-        out.overflow |= f.overflow;
-        out.max_inst = std::max(out.max_inst, f.max_inst);
-        out.visible += f.visible;
-        out.instances += f.instances;
-        out.pairs_contrib += f.pairs_contrib;
-        out.pairs_eval += f.pairs_eval;
-        out.pairs_issued += f.pairs_issued;
+    HIP_CHECK(hipEventSynchronize(ctx->ev_done));
+    ctx->pending = false;
+    const volatile RenderStatus *h = ctx->status_host;
+    out.overflow = h->last.overflow;
+    out.max_inst = h->last.max_inst;
+    out.visible = h->last.visible;
+    out.instances = h->last.instances;
+    out.pairs_contrib = h->last.pairs_contrib;
+    out.pairs_eval = h->last.pairs_eval;
+    out.pairs_issued = h->last.pairs_issued;
+    // overflows of earlier renders on the stream that no call has reported yet
+    const unsigned long long seen = h->overflows;
+    const unsigned long long mine = out.overflow ? 1ull : 0ull;
+    if (seen > ctx->acked_overflows + mine)
+        ctx->capacity_errors += (int)(seen - ctx->acked_overflows - mine);
+    ctx->acked_overflows = std::max(ctx->acked_overflows, seen);
+}
+
+// Grow the instance buffers past `need` instances per chunk (at least
+// doubling); false when they are already at the 2^31 limit.
+bool grow_instances(gs_ctx *ctx, uint64_t need)
+{
+    uint64_t want = std::max<uint64_t>(need + need / 4 + 1024, ctx->inst_cap * 2);
+    if (want > kMaxInstCap) want = kMaxInstCap;
+    if (want <= ctx->inst_cap) return false;
+    ctx->inst_cap = want;
+    return true;
+}
+
+// Without waiting: act on renders that have finished since the last look.
+// An overflow grows the buffers and is kept for gs_render_status; a chunk
+// that came within a fifth of the capacity grows them ahead of time. Either
+// drops the captured graphs (their buffers move).
+void poll_status(gs_ctx *ctx)
+{
+    const volatile RenderStatus *h = ctx->status_host;
+    const unsigned long long seen = h->overflows, max_inst = h->max_inst;
+    bool grow = false;
+    if (seen > ctx->acked_overflows) {
+        ctx->capacity_errors += (int)(seen - ctx->acked_overflows);
+        ctx->acked_overflows = seen;
+        grow = true;
     }
+    if (max_inst * 5 > (unsigned long long)ctx->inst_cap * 4) grow = true;
+    if (grow && grow_instances(ctx, max_inst)) clear_graphs(ctx);
 }
 
 void clear_graphs(gs_ctx *ctx)
@@ -646,7 +733,8 @@ std::string graph_key(int n_cams, const int32_t *scene_ids, int W, int H, const 
 int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const float *poses,
                 const float *intr, int32_t W, int32_t H, float *rgb, float *depth, float *alpha,
                 const gs_render_opts &o, hipStream_t st, const Choice *forced,
-                const std::vector<int32_t> *subset = nullptr, Blend blend = Blend{})
+                const std::vector<int32_t> *subset = nullptr, Blend blend = Blend{},
+                bool may_defer = false)
 {
     uint64_t total = 0;
     int rc = check_scene_ids(ctx, n_cams, scene_ids, &total);
@@ -664,21 +752,25 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
     const int n_lanes =
         (batched && !o.timing) ? (o.streams > 0 ? std::min<int>(o.streams, kLanes) : kLanes) : 1;
     sync_scene_table(ctx);
+    poll_status(ctx);
+    const std::string tail = "|l" + std::to_string(n_lanes) + "|b" +
+                             std::to_string(blend.mode) + ":" + std::to_string(blend.w);
+    // the configuration without buffer addresses: the first render of it waits
+    const std::string config = graph_key(n_cams, scene_ids, W, H, ch, o.near_plane, o.bg, nullptr,
+                                         nullptr, nullptr, nullptr, nullptr, 0, 0, subset) + tail;
+    const bool wait = !may_defer || o.sync || o.timing || o.count_pairs ||
+                      ctx->sized.count(config) == 0;
     ctx->last = gs_stats{};
     int regrows = 0;
     for (int attempt = 0; attempt < 6; ++attempt) {
         StageTimer timer{ctx, st, o.timing != 0};
-        DevFlags f;
         if (!use_graph) {
             // eager: the plain form is the same kernel sequence with one camera per chunk
             std::unique_ptr<Plan> P = make_plan(ctx, n_cams, scene_ids, W, H, ch, subset);
             if (ensure_workspace(ctx, *P, n_lanes)) clear_graphs(ctx);
             enqueue_render(ctx, *P, poses, intr, o.near_plane, o.bg, rgb, depth, alpha, st,
                            ctx->aux_stream, n_lanes, &timer, o.count_pairs != 0, blend);
-            read_flags(ctx, n_lanes, st, f);
         } else {
-            const std::string tail = "|l" + std::to_string(n_lanes) + "|b" +
-                                     std::to_string(blend.mode) + ":" + std::to_string(blend.w);
             std::string key = graph_key(n_cams, scene_ids, W, H, ch, o.near_plane, o.bg, poses,
                                         intr, rgb, depth, alpha, ctx->generation, ctx->inst_cap,
                                         subset) +
@@ -713,8 +805,12 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
                 it = ctx->graphs.emplace(key, std::move(g)).first;
             }
             HIP_CHECK(hipGraphLaunch(it->second->exec, st));
-            read_flags(ctx, n_lanes, st, f);
         }
+        HIP_CHECK(hipEventRecord(ctx->ev_done, st));
+        ctx->pending = true;
+        if (!wait) break;
+        DevFlags f;
+        wait_status(ctx, f);
         ctx->last = gs_stats{};
         ctx->last.visible = (int64_t)f.visible;
         ctx->last.instances = (int64_t)f.instances;
@@ -722,15 +818,14 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
         ctx->last.pairs_evaluated = (int64_t)f.pairs_eval;
         ctx->last.pairs_issued = (int64_t)f.pairs_issued;
         timer.collect(ctx->last);
-        if (!f.overflow) break;
+        if (!f.overflow) {
+            ctx->sized.insert(config);
+            break;
+        }
         // grow the instance buffers past the largest chunk's need and retry
         ++regrows;
-        uint64_t want = std::max<uint64_t>((uint64_t)f.max_inst + f.max_inst / 4 + 1024,
-                                           ctx->inst_cap * 2);
-        if (want > kMaxInstCap) want = kMaxInstCap;
-        if (want <= ctx->inst_cap)
+        if (!grow_instances(ctx, f.max_inst))
             return fail(ctx, GS_ERR_CAPACITY, "instance count per chunk exceeds 2^31");
-        ctx->inst_cap = want;
         clear_graphs(ctx);
         if (attempt == 5) return fail(ctx, GS_ERR_CAPACITY, "instance buffers kept overflowing");
     }
@@ -742,6 +837,7 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
     ctx->last.lds_batch = ch.batch;
     ctx->last.chunk_cams = ch.chunk;
     ctx->last.persistent = ch.persistent;
+    ctx->last_deferred = !wait;
     return GS_OK;
 }
 
@@ -836,19 +932,17 @@ int render_backward_impl(gs_ctx *ctx, int32_t scene_id, int32_t n_cams, const fl
             b.d_sh = d_sh;
             launch_bwd_gauss(sc.deg, b, st);
         }
+        enqueue_status(ctx, 1, st);
         HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipEventRecord(ctx->ev_done, st));
         DevFlags f;
-        read_flags(ctx, 1, st, f);
+        wait_status(ctx, f);
         ctx->last.visible = (int64_t)f.visible;
         ctx->last.instances = (int64_t)f.instances;
         if (!f.overflow) break;
         ++regrows;
-        uint64_t want = std::max<uint64_t>((uint64_t)f.max_inst + f.max_inst / 4 + 1024,
-                                           ctx->inst_cap * 2);
-        if (want > kMaxInstCap) want = kMaxInstCap;
-        if (want <= ctx->inst_cap)
+        if (!grow_instances(ctx, f.max_inst))
             return fail(ctx, GS_ERR_CAPACITY, "instance count per chunk exceeds 2^31");
-        ctx->inst_cap = want;
         clear_graphs(ctx);
         if (attempt == 5) return fail(ctx, GS_ERR_CAPACITY, "instance buffers kept overflowing");
     }
@@ -1145,8 +1239,13 @@ int gs_create(int hip_device, gs_ctx **out)
             ctx->slot_budget = std::min<uint64_t>(std::max<uint64_t>(b, uint64_t(1) << 20),
                                                   uint64_t(1) << 30);
         }
-        HIP_CHECK(hipHostMalloc((void **)&ctx->host_flags, kLanes * sizeof(DevFlags),
-                                hipHostMallocDefault));
+        HIP_CHECK(hipHostMalloc((void **)&ctx->status_host, sizeof(RenderStatus),
+                                hipHostMallocMapped));
+        std::memset((void *)ctx->status_host, 0, sizeof(RenderStatus));
+        HIP_CHECK(hipHostGetDevicePointer((void **)&ctx->status_host_dev, ctx->status_host, 0));
+        ctx->status_dev.reserve(1);
+        HIP_CHECK(hipMemset(ctx->status_dev.p, 0, sizeof(RenderStatus)));
+        HIP_CHECK(hipEventCreateWithFlags(&ctx->ev_done, hipEventDisableTiming));
         HIP_CHECK(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
         for (int l = 0; l < kLanes - 1; ++l) {
             HIP_CHECK(hipStreamCreateWithFlags(&ctx->capture_aux[l], hipStreamNonBlocking));
@@ -1181,7 +1280,8 @@ int gs_destroy(gs_ctx *ctx)
         if (ctx->capture_aux[l]) (void)hipStreamDestroy(ctx->capture_aux[l]);
         if (ctx->aux_stream[l]) (void)hipStreamDestroy(ctx->aux_stream[l]);
     }
-    if (ctx->host_flags) (void)hipHostFree(ctx->host_flags);
+    if (ctx->ev_done) (void)hipEventDestroy(ctx->ev_done);
+    if (ctx->status_host) (void)hipHostFree(ctx->status_host);
     delete ctx;
     return GS_OK;
 }
@@ -1308,6 +1408,7 @@ int gs_upload_scene(gs_ctx *ctx, const gs_scene_desc *d, int32_t *scene_id_out)
         }
         ctx->scenes[id] = std::move(s);
         ctx->scenes_dirty = true;
+        ctx->sized.clear();
         *scene_id_out = id;
         return GS_OK;
     });
@@ -1325,6 +1426,7 @@ int gs_release_scene(gs_ctx *ctx, int32_t scene_id)
         HIP_CHECK(hipDeviceSynchronize());
         ctx->scenes[scene_id].reset();
         ctx->scenes_dirty = true;
+        ctx->sized.clear();
         return GS_OK;
     });
 }
@@ -1353,7 +1455,7 @@ int gs_render_batch(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const
     return guarded(ctx, [&] {
         HIP_CHECK(hipSetDevice(ctx->device));
         return render_impl(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb, depth,
-                           alpha, o, (hipStream_t)stream, nullptr);
+                           alpha, o, (hipStream_t)stream, nullptr, nullptr, Blend{}, true);
     });
 }
 
@@ -1543,8 +1645,49 @@ int gs_peak_probe(gs_ctx *ctx, int32_t kind, double *rate_out)
 int gs_last_stats(gs_ctx *ctx, gs_stats *out)
 {
     if (!ctx || !out) return GS_ERR_INVALID_ARG;
-    *out = ctx->last;
-    return GS_OK;
+    return guarded(ctx, [&] {
+        if (ctx->last_deferred) {
+            // the last render returned before it finished: wait for its counts
+            HIP_CHECK(hipSetDevice(ctx->device));
+            DevFlags f;
+            wait_status(ctx, f);
+            ctx->last.visible = (int64_t)f.visible;
+            ctx->last.instances = (int64_t)f.instances;
+            ctx->last.pairs_contrib = (int64_t)f.pairs_contrib;
+            ctx->last.pairs_evaluated = (int64_t)f.pairs_eval;
+            ctx->last.pairs_issued = (int64_t)f.pairs_issued;
+            ctx->last_deferred = false;
+        }
+        *out = ctx->last;
+        out->instance_capacity = (int64_t)ctx->inst_cap;
+        return GS_OK;
+    });
+}
+
+int gs_render_status(gs_ctx *ctx, int32_t wait)
+{
+    if (!ctx) return GS_ERR_INVALID_ARG;
+    return guarded(ctx, [&] {
+        HIP_CHECK(hipSetDevice(ctx->device));
+        if (wait && ctx->pending) {
+            HIP_CHECK(hipEventSynchronize(ctx->ev_done));
+            ctx->pending = false;
+        } else if (ctx->pending) {
+            const hipError_t q = hipEventQuery(ctx->ev_done);
+            if (q != hipSuccess && q != hipErrorNotReady)
+                throw GsError(GS_ERR_HIP, std::string("render failed: ") + hipGetErrorString(q));
+        }
+        poll_status(ctx);
+        if (ctx->capacity_errors > 0) {
+            const int n = ctx->capacity_errors;
+            ctx->capacity_errors = 0;
+            return fail(ctx, GS_ERR_CAPACITY,
+                        std::to_string(n) + " render(s) overflowed the instance buffers and are "
+                        "incomplete; the buffers now hold " + std::to_string(ctx->inst_cap) +
+                        " instances per chunk: render again");
+        }
+        return GS_OK;
+    });
 }
 
 int gs_set_instance_capacity(gs_ctx *ctx, int64_t cap)
@@ -1556,6 +1699,14 @@ int gs_set_instance_capacity(gs_ctx *ctx, int64_t cap)
         HIP_CHECK(hipSetDevice(ctx->device));
         HIP_CHECK(hipDeviceSynchronize());
         clear_graphs(ctx);
+        ctx->sized.clear();
+        // the largest chunk seen so far no longer drives the buffer size (the
+        // device is idle here, so the status can be rewritten)
+        RenderStatus st{};
+        HIP_CHECK(hipMemcpy(&st, ctx->status_dev.p, sizeof st, hipMemcpyDeviceToHost));
+        st.max_inst = 0;
+        HIP_CHECK(hipMemcpy(ctx->status_dev.p, &st, sizeof st, hipMemcpyHostToDevice));
+        ctx->status_host->max_inst = 0;
         for (Lane &L : ctx->lanes)
             for (int i = 0; i < 2; ++i) {
                 L.ikeys[i].release();

@@ -267,6 +267,60 @@ def test_capacity_regrow_path(gpu_renderer, w1):
         assert bool((x == y).all())
 
 
+def test_async_renders_back_to_back_equal_waiting_renders(gpu_renderer, w1):
+    """Two renders of the same cameras with different poses enqueued back to
+    back without waiting (eager and graph-replayed), one synchronisation,
+    both outputs bitwise equal to renders that waited."""
+    import torch
+    sc, sid, cams = w1
+    ids = [sid] * 8
+    K = cams["intrinsics"][:8]
+    Pa, Pb = cams["poses"][:8], cams["poses"][8:16]
+    refs = [[t.cpu().numpy() for t in gpu_renderer.render(ids, P, K, 640, 480, sync=True)]
+            for P in (Pa, Pb)]
+    for use_graph in (False, True):
+        P = torch.as_tensor(Pa).cuda()
+        outs = [gpu_renderer.alloc_outputs(8, 640, 480) for _ in range(2)]
+        gpu_renderer.render(ids, P, K, 640, 480, out=outs[0], use_graph=use_graph)  # sizes
+        gpu_renderer.render(ids, P, K, 640, 480, out=outs[1], use_graph=use_graph)  # sizes
+        P2 = torch.as_tensor(Pb).cuda()
+        gpu_renderer.render(ids, P, K, 640, 480, out=outs[0], use_graph=use_graph)
+        gpu_renderer.render(ids, P2, K, 640, 480, out=outs[1], use_graph=use_graph)
+        torch.cuda.synchronize()
+        gpu_renderer.status(wait=True)
+        for ref, got in zip(refs, outs):
+            for x, y in zip(ref, got):
+                assert np.array_equal(x, y.cpu().numpy())
+    gpu_renderer.drop_graphs()
+
+
+def test_async_overflow_is_reported_and_next_render_complete(gpu_renderer, w1):
+    """A render that returns without waiting and overflows the instance
+    buffers is reported by gs_render_status (GS_ERR_CAPACITY), which leaves
+    the buffers grown: the next render is complete."""
+    import paper_2510_15352_amd as gs
+    sc, sid, cams = w1
+    ids = [sid] * 4
+    P, K = cams["poses"][:4], cams["intrinsics"][:4]
+    # 100 m above the terrain looking up (+z): nothing in front of the cameras
+    away = np.zeros_like(P)
+    away[:, :, :3] = np.eye(3)
+    away[:, 2, 3] = 100.0
+    ref = [t.cpu().numpy() for t in gpu_renderer.render(ids, P, K, 640, 480, sync=True)]
+    gpu_renderer.set_instance_capacity(1000)
+    gpu_renderer.render(ids, away, K, 640, 480)        # first of the configuration: waits
+    assert gpu_renderer.stats()["instances"] < 1000
+    gpu_renderer.render(ids, P, K, 640, 480)           # does not wait; overflows
+    with pytest.raises(gs.GsError) as e:
+        gpu_renderer.status(wait=True)
+    assert e.value.code == -4
+    assert gpu_renderer.stats()["instance_capacity"] > 1000
+    got = gpu_renderer.render(ids, P, K, 640, 480)
+    gpu_renderer.status(wait=True)
+    for x, y in zip(ref, got):
+        assert np.array_equal(x, y.cpu().numpy())
+
+
 def test_empty_cameras_between_visible_ones(gpu_renderer, w0):
     """Cameras with no visible Gaussian leave empty per-camera segments in the
     depth and tile sorts, here at the start, middle and end of chunks."""
