@@ -295,8 +295,12 @@ int gs_debug_project(gs_ctx *ctx, int32_t scene_id, const float *pose, const flo
  * Time the batched form over candidate (tile shape, LDS batch, chunk size,
  * persistent) choices for this camera batch and remember the fastest for
  * later renders with the same (W, H, camera count, scene-size bucket).
- * The table is appended to `cache_path` (JSON lines) when it is not NULL.
- * Arguments as gs_render_batch (outputs are scratch). Synchronous.
+ * With `cache_path` (JSON lines, one object per tuning: "key" = GPU
+ * architecture, compute units, W, H, camera count and scene-size bucket;
+ * "best" = TWxTH/bB/cC/pP; the timing table), the last entry of the file for
+ * this key is used without timing anything; otherwise the tuning runs and
+ * its entry is appended. Arguments as gs_render_batch (outputs are
+ * scratch). Synchronous.
  */
 int gs_autotune(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const float *poses,
                 const float *intrinsics, int32_t width, int32_t height, float *rgb, float *depth,

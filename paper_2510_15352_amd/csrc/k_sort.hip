@@ -102,10 +102,12 @@ __global__ __launch_bounds__(kBS) void k_scan_reduce(Load ld, const uint32_t *n_
                                                      uint32_t n_host, int nb,
                                                      uint32_t *__restrict__ partial)
 {
-    __shared__ uint32_t s_wave[kWaves];
+    __shared__ unsigned long long s_sum[kWaves];
     uint32_t start, end;
     block_range(count_of(n_dev, n_host), nb, start, end);
-    uint32_t s = 0;
+    // 64-bit sums: a block's total saturates at 2^32 - 1 instead of wrapping
+    // (the emission then sees a count past any capacity and flags it)
+    unsigned long long s = 0;
     // eight loads in flight per thread (indices past the end read the last
     // element, which is then not counted, so no load sits under a branch)
     for (uint32_t i0 = start + threadIdx.x; i0 < end; i0 += 8u * kBS) {
@@ -115,9 +117,16 @@ __global__ __launch_bounds__(kBS) void k_scan_reduce(Load ld, const uint32_t *n_
 #pragma unroll
         for (int u = 0; u < 8; ++u) s += i0 + (uint32_t)u * kBS < end ? v[u] : 0u;
     }
-    uint32_t t;
-    block_excl_scan<kWaves>(s, t, s_wave);
-    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) s += __shfl_down(s, d, 64);
+    if (__lane_id() == 0) s_sum[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) t += s_sum[w];
+        partial[blockIdx.x] = t > 0xffffffffull ? 0xffffffffu : (uint32_t)t;
+    }
 }
 
 // Exclusive scan of the nb (<= 4096) block sums by one 1024-thread block,
@@ -125,23 +134,42 @@ __global__ __launch_bounds__(kBS) void k_scan_reduce(Load ld, const uint32_t *n_
 __global__ __launch_bounds__(1024) void k_scan_partials(uint32_t *__restrict__ partial, int nb,
                                                         uint32_t *__restrict__ total_out)
 {
-    __shared__ uint32_t s_wave[16];
-    uint32_t v[4], sum = 0;
+    // in 64 bits, saturated at 2^32 - 1 when stored (never wraps to a small count)
+    __shared__ unsigned long long s_wave[16];
+    uint32_t v[4];
+    unsigned long long sum = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int i = (int)threadIdx.x * 4 + q;
         v[q] = i < nb ? partial[i] : 0u;
         sum += v[q];
     }
-    uint32_t total;
-    uint32_t ex = block_excl_scan<16>(sum, total, s_wave);
+    const uint32_t lane = __lane_id();
+    unsigned long long inc = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned long long t = __shfl_up(inc, d, 64);
+        if (lane >= (uint32_t)d) inc += t;
+    }
+    const int wave = (int)threadIdx.x >> 6;
+    if (lane == 63) s_wave[wave] = inc;
+    __syncthreads();
+    unsigned long long ex = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+        const unsigned long long t = s_wave[w];
+        ex += w < wave ? t : 0ull;
+        total += t;
+    }
+    ex += inc - sum;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int i = (int)threadIdx.x * 4 + q;
-        if (i < nb) partial[i] = ex;
+        if (i < nb) partial[i] = ex > 0xffffffffull ? 0xffffffffu : (uint32_t)ex;
         ex += v[q];
     }
-    if (threadIdx.x == 0 && total_out) *total_out = total;
+    if (threadIdx.x == 0 && total_out)
+        *total_out = total > 0xffffffffull ? 0xffffffffu : (uint32_t)total;
 }
 
 template <class Load>
@@ -293,7 +321,7 @@ __global__ __launch_bounds__(kBS) void k_emit_down(
     __shared__ int s_cam;
     uint32_t start, end;
     block_range(*n_dev, nb, start, end);
-    uint32_t base = partial[blockIdx.x];
+    uint64_t base = partial[blockIdx.x];  // 64-bit: positions past 2^32 stay past cap
     const uint32_t lane = __lane_id();
     // first camera whose records start inside this block's range or later
     // (vis_start is non-decreasing; vis_start[n_cams] = number of records)
@@ -339,7 +367,7 @@ __global__ __launch_bounds__(kBS) void k_emit_down(
         // share the offset of the next camera's first record)
         const uint32_t lim = min(t0 + (uint32_t)kBS, end);
         while (cam_first < lim) {
-            if (i == cam_first) inst_start[cam] = min(base + ex, kept);
+            if (i == cam_first) inst_start[cam] = (uint32_t)min(base + ex, (uint64_t)kept);
             ++cam;
             cam_first = cam < n_cams ? vis_start[cam] : ~0u;
         }
@@ -359,7 +387,7 @@ __global__ __launch_bounds__(kBS) void k_emit_down(
             const uint32_t key0 = __shfl(kbase, r, 64);
             const uint32_t sl = __shfl(slot, r, 64);
             const uint32_t ty = j / bw, tx = j - ty * bw;
-            const uint32_t o = base + first + k;
+            const uint64_t o = base + first + k;
             if (k < wave_total && o < cap) {
                 ikeys[o] = key0 + ty * (uint32_t)tiles_x + tx;
                 ivals[o] = sl;

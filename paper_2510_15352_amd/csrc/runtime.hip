@@ -204,6 +204,7 @@ struct GraphEntry {
 struct gs_ctx {
     int device = 0;
     int cu_count = 0;
+    std::string arch;  // gcnArchName of the device (autotune cache key)
     unsigned char *scratch = nullptr;  // this device's copy of the scratch array
     std::string err;
     std::vector<std::unique_ptr<Scene>> scenes;
@@ -1233,6 +1234,7 @@ int gs_create(int hip_device, gs_ctx **out)
         hipDeviceProp_t prop;
         HIP_CHECK(hipGetDeviceProperties(&prop, hip_device));
         ctx->cu_count = prop.multiProcessorCount;
+        ctx->arch = prop.gcnArchName;
         {
             constexpr uint64_t kSlotBytes = 84;
             const uint64_t b = (uint64_t)prop.totalGlobalMem / (3 * kLanes * kSlotBytes);
@@ -1778,6 +1780,44 @@ int gs_autotune(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
         uint64_t total = 0;
         int r = check_scene_ids(ctx, n_cams, scene_ids, &total);
         if (r) return r;
+        char key[128];
+        snprintf(key, sizeof key, "%d:%d:%d:%d", width, height, n_cams, bits_for(total + 1));
+        // the cache key adds the GPU (architecture and compute units)
+        const std::string ckey = ctx->arch.substr(0, ctx->arch.find(':')) + ":" +
+                                 std::to_string(ctx->cu_count) + "cu:" + key;
+        if (cache_path) {
+            // the last entry for this key in the cache file, if any, is used as is
+            FILE *f = fopen(cache_path, "r");
+            bool found = false;
+            Choice cached;
+            if (f) {
+                char line[8192];
+                const std::string want = "\"key\": \"" + ckey + "\"";
+                while (fgets(line, sizeof line, f)) {
+                    if (!strstr(line, want.c_str())) continue;
+                    const char *b = strstr(line, "\"best\": \"");
+                    Choice c;
+                    if (b && sscanf(b + 9, "%dx%d/b%d/c%d/p%d", &c.tw, &c.th, &c.batch, &c.chunk,
+                                    &c.persistent) == 5 &&
+                        raster_supported(c.tw, c.th, c.batch) && c.chunk >= 1 &&
+                        c.chunk <= kMaxChunkCams) {
+                        cached = c;
+                        found = true;
+                    }
+                }
+                fclose(f);
+            }
+            if (found) {
+                ctx->tuned[key] = cached;
+                ctx->last = gs_stats{};
+                ctx->last.tile_w = cached.tw;
+                ctx->last.tile_h = cached.th;
+                ctx->last.lds_batch = cached.batch;
+                ctx->last.chunk_cams = cached.chunk;
+                ctx->last.persistent = cached.persistent;
+                return GS_OK;
+            }
+        }
         gs_render_opts o;
         gs_default_opts(&o);
         std::vector<Choice> cands;
@@ -1844,13 +1884,11 @@ int gs_autotune(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        char key[128];
-        snprintf(key, sizeof key, "%d:%d:%d:%d", width, height, n_cams, bits_for(total + 1));
         ctx->tuned[key] = best;
         if (cache_path) {
             FILE *f = fopen(cache_path, "a");
             if (f) {
-                fprintf(f, "{\"key\": \"%s\", \"best\": \"%s\", \"best_ms\": %.4f, \"table\": {", key,
+                fprintf(f, "{\"key\": \"%s\", \"best\": \"%s\", \"best_ms\": %.4f, \"table\": {", ckey.c_str(),
                         choice_key(best).c_str(), best_ms);
                 for (size_t i = 0; i < table.size(); ++i)
                     fprintf(f, "%s\"%s\": %.4f", i ? ", " : "", choice_key(table[i].first).c_str(),

@@ -83,3 +83,39 @@ def test_autotuner_choice_is_used_and_bitwise_identical(gpu_renderer):
         assert np.array_equal(x, y.cpu().numpy())
     torch.cuda.synchronize()
     gpu_renderer.release_scene(sid)
+
+
+def test_autotune_cache_is_read_back(gpu_renderer, tmp_path):
+    """gs_autotune appends its result to the cache file under a key holding
+    the GPU architecture; a fresh context given the same file uses the last
+    entry for its key without tuning (here an entry edited to another valid
+    choice, which the next render must use)."""
+    import json
+    import paper_2510_15352_amd as gs
+    sc = scenegen.make_scene(1)
+    cams = scenegen.make_cameras(1)
+    P, K = cams["poses"][:16], cams["intrinsics"][:16]
+    path = str(tmp_path / "tune.jsonl")
+    for step in range(2):
+        r = gs.Renderer(0)
+        try:
+            sid = r.upload_scene(sc)
+            ids = [sid] * 16
+            if step == 1:
+                entry = json.loads(open(path).read().splitlines()[-1])
+                entry["best"] = "32x8/b64/c256/p0"
+                with open(path, "a") as f:
+                    f.write(json.dumps(entry) + "\n")
+            r.autotune(ids, P, K, 640, 480, cache_path=path)
+            lines = open(path).read().splitlines()
+            key = json.loads(lines[0])["key"]
+            print("autotune cache key", key)
+            assert key.startswith("gfx950:") and key.endswith(":640:480:16:18")
+            assert len(lines) == (1 if step == 0 else 2)   # nothing appended when read back
+            r.render(ids, P, K, 640, 480)
+            st = r.stats()
+            if step == 1:
+                assert (st["tile_w"], st["tile_h"], st["lds_batch"], st["chunk_cams"],
+                        st["persistent"]) == (32, 8, 64, 256, 0)
+        finally:
+            r.close()
