@@ -296,6 +296,99 @@ def network_roofline(r, scene_ids, P, K, W, H, n, torch):
             "hbm_frac": gbytes / (ms / 1e3) / 8000.0}
 
 
+def stress_leg(args, r, torch):
+    """The stress workload (one 3M-Gaussian scene, 8192 cameras at 320x240)
+    over a few consecutive sim steps: every camera advances along its
+    trajectory each step, the step's poses are copied into the buffer the
+    captured graph reads and the graph is replayed (every stage recomputed).
+    Fixed choice (16x8 tiles, LDS batch 64: the autotuner's pick for this
+    workload), so the leg needs no tuning time. Also the pair counts of one
+    step (instrumented raster)."""
+    import scenegen
+    k = 4
+    w = scenegen.workload(k)
+    t = time.time()
+    sc = scenegen.make_scene(k, 0)
+    traj = scenegen.camera_steps(k, args.stress_steps)
+    log(f"stress leg: generated {len(sc['opacity'])} Gaussians and {args.stress_steps} steps of "
+        f"{w.n_cams} cameras in {time.time() - t:.1f}s")
+    sid = r.upload_scene(sc)
+    n, W, H = w.n_cams, w.width, w.height
+    ids = np.full(n, sid, np.int32)
+    trajd = torch.as_tensor(traj["poses"]).cuda()
+    P = trajd[0].clone()
+    K = torch.as_tensor(traj["intrinsics"]).cuda()
+    out = r.alloc_outputs(n, W, H, alpha=False)
+    kw = dict(tile=(16, 8), lds_batch=64, persistent=0)
+
+    def step(i):
+        P.copy_(trajd[i % args.stress_steps])
+        r.render(ids, P, K, W, H, out=out, use_graph=True, **kw)
+
+    for i in range(2):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.stress_steps):
+        step(i)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.stress_steps * 1e3
+    st = r.stats()
+    P.copy_(trajd[0])
+    r.render(ids, P, K, W, H, out=out, count_pairs=True, **kw)
+    sc_ = r.stats()
+    pairs, evals, issued = sc_["pairs_contrib"], sc_["pairs_evaluated"], sc_["pairs_issued"]
+    b_g = 44 + 12 * (w.sh_degree + 1) ** 2
+    alg = 16.0 * W * H * n + float(len(sc["opacity"])) * b_g + 24.0 * float(st["instances"])
+    log(f"stress leg: {ms:.1f} ms/step over {args.stress_steps} consecutive steps, "
+        f"{n / ms * 1e3:.0f} frames/s; evaluated/contributing {evals / max(pairs, 1):.2f}, "
+        f"issued/contributing {issued / max(pairs, 1):.2f}")
+    r.drop_graphs()
+    r.release_scene(sid)
+    del out, trajd
+    return {"workload": w.name, "steps": args.stress_steps, "ms_per_step": ms,
+            "frames_per_s": n / ms * 1e3, "form": "batched, hipGraph replay, poses advanced "
+            "every sim step", "choice": {k_: st[k_] for k_ in ("tile_w", "tile_h", "lds_batch",
+                                                                "chunk_cams", "persistent")},
+            "pairs_per_step": pairs, "eval_over_contrib": evals / max(pairs, 1),
+            "issued_over_contrib": issued / max(pairs, 1),
+            "hbm_algorithmic_GB_per_s": alg / (ms * 1e-3) / 1e9}
+
+
+def backward_leg(args, r, torch):
+    """The backward pass (gradients of RGB, depth and alpha with respect to
+    every Gaussian parameter) over the 64 cameras of the 200k-Gaussian SH-3
+    terrain scene at 640x480, random upstream gradients; each call waits
+    for its result."""
+    import scenegen
+    sc = scenegen.make_scene(1)
+    cams = scenegen.make_cameras(1)
+    sid = r.upload_scene(sc)
+    n, W, H = len(cams["poses"]), cams["width"], cams["height"]
+    P = torch.as_tensor(cams["poses"]).cuda()
+    K = torch.as_tensor(cams["intrinsics"]).cuda()
+    g = torch.Generator(device="cuda").manual_seed(5)
+    gr = torch.randn((n, H, W, 3), device="cuda", generator=g)
+    gd = 0.1 * torch.randn((n, H, W), device="cuda", generator=g)
+    ga = torch.randn((n, H, W), device="cuda", generator=g)
+    r.render_backward(sid, P, K, W, H, gr, gd, ga)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r.render_backward(sid, P, K, W, H, gr, gd, ga)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    r.render([sid] * n, P, K, W, H, use_graph=False)
+    ms_fwd = time_steps(lambda: r.render([sid] * n, P, K, W, H), 3, torch) * 1e3
+    r.release_scene(sid)
+    log(f"backward: {ms:.1f} ms for {n} cameras of 640x480 ({n / ms * 1e3:.0f} frames/s), "
+        f"forward {ms_fwd:.1f} ms")
+    return {"workload": "slab200k_sh3_64cams_640x480", "cams": n, "ms": ms,
+            "frames_per_s": n / ms * 1e3, "forward_ms": ms_fwd,
+            "upstream": "random normal dL/dRGB, 0.1 x normal dL/ddepth, normal dL/dalpha"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -321,6 +414,11 @@ def main():
     ap.add_argument("--psnr-target", type=float, default=35.0)
     ap.add_argument("--oracle-frames", type=int, default=128,
                     help="evaluation frames of the learned form checked against the FP64 oracle")
+    ap.add_argument("--stress-steps", type=int, default=10,
+                    help="consecutive sim steps of the stress workload timed beside the default "
+                         "workload (0: skip that leg)")
+    ap.add_argument("--no-backward", action="store_true",
+                    help="skip timing the backward pass")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device a few times and exit (reference "
                          "kernel for scaling the HBM byte counters)")
@@ -488,6 +586,11 @@ def main():
         if "plain" in forms:
             forms["learned"]["speedup_over_plain"] = (forms["plain"]["ms_per_step"] /
                                                       forms["learned"]["ms_per_step"])
+
+    if not args.only_batched and args.workload == 2 and args.stress_steps > 0:
+        forms["stress_workload4"] = stress_leg(args, r, torch)
+    if not args.only_batched and not args.no_backward and args.workload == 2:
+        forms["backward"] = backward_leg(args, r, torch)
 
     cpu = None
     if not args.no_cpu:
