@@ -293,8 +293,11 @@ int gs_debug_project(gs_ctx *ctx, int32_t scene_id, const float *pose, const flo
 
 /*
  * Time the batched form over candidate (tile shape, LDS batch, chunk size,
- * persistent) choices for this camera batch and remember the fastest for
- * later renders with the same (W, H, camera count, scene-size bucket).
+ * persistent) choices for this camera batch and remember the pick for
+ * later renders with the same (W, H, camera count, scene-size bucket): the
+ * candidates are tried in a fixed order of preference (the default choice
+ * first), and the earliest one within 2% of the fastest is picked, so noise
+ * in the timings does not flip the pick between near-equal choices.
  * With `cache_path` (JSON lines, one object per tuning: "key" = GPU
  * architecture, compute units, W, H, camera count and scene-size bucket;
  * "best" = TWxTH/bB/cC/pP; the timing table), the last entry of the file for

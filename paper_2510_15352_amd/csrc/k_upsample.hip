@@ -17,6 +17,7 @@
 //   weight grad  dW[co][t][ci] = sum_p dY[p][co] X[p + off(t)][ci]: M = 16 co,
 //                N = 16 (t, ci), K = 32 pixels; one partial per block, summed
 //                in a fixed order by a second kernel (deterministic).
+#include <algorithm>
 #include <cmath>
 
 #include "gs_device.h"
@@ -392,14 +393,27 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const uint16_t *__restric
     }
 }
 
-// grad[j] = sum over blocks of part[blk][j], in block order.
-__global__ void k_sum_partials(const float *__restrict__ part, int nblk, int len,
-                               float *__restrict__ grad)
+// grad[j] = sum over blocks of part[blk][j] in two fixed-order stages: the
+// blocks are cut into runs of L; stage one sums run s (in block order) into
+// its own first row, part[s L][j] (only the thread summing that run reads
+// it), stage two sums those rows in run order.
+__global__ void k_sum_runs(float *__restrict__ part, int nblk, int len, int L)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= len) return;
+    const int b0 = (int)blockIdx.y * L, b1 = min(b0 + L, nblk);
+    float s = 0.0f;
+    for (int b = b0; b < b1; ++b) s += part[(int64_t)b * len + j];
+    part[(int64_t)b0 * len + j] = s;
+}
+
+__global__ void k_sum_run_heads(const float *__restrict__ part, int nruns, int len, int L,
+                                float *__restrict__ grad)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= len) return;
     float s = 0.0f;
-    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * len + j];
+    for (int r = 0; r < nruns; ++r) s += part[(int64_t)r * L * len + j];
     grad[j] = s;
 }
 
@@ -638,10 +652,15 @@ void launch_up_wgrad(int cin, int cout, const uint16_t *x, const uint16_t *dy, i
                            part, partb);
 }
 
-void launch_sum_partials(const float *part, int nblk, int len, float *grad, hipStream_t st)
+void launch_sum_partials(float *part, int nblk, int len, float *grad, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_sum_partials, dim3((len + 255) / 256), dim3(256), 0, st, part, nblk, len,
-                       grad);
+    // runs of at least 32 blocks, at most 256 runs
+    const int nr0 = std::max(1, std::min(256, nblk / 32));
+    const int L = (nblk + nr0 - 1) / nr0;
+    const int nruns = (nblk + L - 1) / L;
+    const unsigned gx = (unsigned)((len + 255) / 256);
+    hipLaunchKernelGGL(k_sum_runs, dim3(gx, (unsigned)nruns), dim3(256), 0, st, part, nblk, len, L);
+    hipLaunchKernelGGL(k_sum_run_heads, dim3(gx), dim3(256), 0, st, part, nruns, len, L, grad);
 }
 
 int up_head_blocks(int n, int h, int w) { return (int)(((int64_t)n * h * w * 16 + 255) / 256); }

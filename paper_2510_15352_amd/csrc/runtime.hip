@@ -1820,10 +1820,14 @@ int gs_autotune(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
         }
         gs_render_opts o;
         gs_default_opts(&o);
+        // candidates in order of preference, the library default first:
+        // among choices timed within 2% of the fastest the earliest wins, so
+        // timing noise does not flip the pick between near-equal choices
         std::vector<Choice> cands;
+        cands.push_back(Choice{});
         const int shapes[][2] = {{16, 16}, {32, 8}, {16, 8}, {8, 8}, {32, 16}};
-        const int batches[] = {64, 128, 256};
-        const int chunks[] = {256, 512, 1024};
+        const int batches[] = {128, 64, 256};
+        const int chunks[] = {512, 1024, 256};
         for (auto &s : shapes)
             for (int b : batches)
                 if (raster_supported(s[0], s[1], b))
@@ -1834,8 +1838,9 @@ int gs_autotune(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
                         c.batch = b;
                         c.chunk = 512;
                         c.persistent = p;
-                        cands.push_back(c);
+                        if (choice_key(c) != choice_key(cands[0])) cands.push_back(c);
                     }
+        constexpr float kTie = 1.02f;
         hipEvent_t e0, e1;
         HIP_CHECK(hipEventCreate(&e0));
         HIP_CHECK(hipEventCreate(&e1));
@@ -1857,31 +1862,27 @@ int gs_autotune(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
             }
             return best;
         };
-        Choice best;
-        float best_ms = 1e30f;
         std::vector<std::pair<Choice, float>> table;
-        for (const Choice &c : cands) {
-            float ms = time_choice(c, 2);
-            table.push_back({c, ms});
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = c;
-            }
-        }
-        // the chunk sizes differ by a few percent: the best shape and its
+        auto pick = [&](size_t from) {
+            float fastest = 1e30f;
+            for (size_t i = from; i < table.size(); ++i) fastest = std::min(fastest, table[i].second);
+            for (size_t i = from; i < table.size(); ++i)
+                if (table[i].second <= fastest * kTie) return table[i];
+            return table[from];
+        };
+        for (const Choice &c : cands) table.push_back({c, time_choice(c, 2)});
+        // the chunk sizes differ by a few percent: the picked shape and its
         // chunk variants are timed again over more replays
-        const Choice shape = best;
-        best_ms = 1e30f;
+        const Choice shape = pick(0).first;
+        const size_t second = table.size();
         for (int ck : chunks) {
             Choice c = shape;
             c.chunk = ck;
-            float ms = time_choice(c, 6);
-            table.push_back({c, ms});
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = c;
-            }
+            table.push_back({c, time_choice(c, 6)});
         }
+        const std::pair<Choice, float> chosen = pick(second);
+        const Choice best = chosen.first;
+        const float best_ms = chosen.second;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         ctx->tuned[key] = best;

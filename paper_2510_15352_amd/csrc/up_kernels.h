@@ -28,7 +28,7 @@ void launch_up_conv(int cin, int cout, int epi, const uint16_t *in, const uint16
                     float *depth = nullptr);
 void launch_up_wgrad(int cin, int cout, const uint16_t *x, const uint16_t *dy, int n, int h,
                      int w, float *part, float *partb, hipStream_t st);
-void launch_sum_partials(const float *part, int nblk, int len, float *grad, hipStream_t st);
+void launch_sum_partials(float *part, int nblk, int len, float *grad, hipStream_t st);
 void launch_up_head(bool train, const float *x0f, const float *y, int h, int w, int n,
                     float *rgb, float *depth, const float *t_rgb, const float *t_depth,
                     float *loss_part, uint16_t *dy, hipStream_t st);
