@@ -408,6 +408,8 @@ def main():
     ap.add_argument("--choice", type=int, nargs=4, default=None, metavar=("TW", "TH", "B", "C"),
                     help="render with tile TWxTH, LDS batch B, C cameras per chunk (grid "
                          "raster) instead of the autotuner's choice (for profiling)")
+    ap.add_argument("--form", type=int, default=0, choices=[0, 1],
+                    help="raster form with --choice: 0 grid, 1 persistent work queue")
     ap.add_argument("--train-pairs", type=int, default=100_000)
     ap.add_argument("--train-batch", type=int, default=64)
     ap.add_argument("--calib-cams", type=int, default=512)
@@ -463,7 +465,7 @@ def main():
     choice_kw = {}
     if args.choice:
         tw, th, b, c = args.choice
-        choice_kw = dict(tile=(tw, th), lds_batch=b, chunk_cams=c, persistent=0)
+        choice_kw = dict(tile=(tw, th), lds_batch=b, chunk_cams=c, persistent=args.form)
     if not args.no_autotune and not args.choice:
         t = time.time()
         out_dir = os.path.join(ROOT, "gpurun_out")
@@ -535,8 +537,9 @@ def main():
         raster_launch_ms = stage_ms["raster"] / max(stage_n["raster"], 1)
         pairs_per_launch = pairs / max(stage_n["raster"] / eager_steps, 1)
         achieved = pairs_per_launch * SLOTS_PER_PAIR / (raster_launch_ms * 1e-3)
-        kname = "gs::k_raster<%d, %d, %d>" % (st_graph["tile_w"], st_graph["tile_h"],
-                                              st_graph["lds_batch"])
+        kname = "gs::%s<%d, %d, %d>" % (
+            {0: "k_raster", 1: "k_raster_persistent"}[st_graph["persistent"]],
+            st_graph["tile_w"], st_graph["tile_h"], st_graph["lds_batch"])
         launches = stage_n["raster"] / eager_steps
         traffic, traffic_cams = measured_traffic(kname, n / max(launches, 1))
         roofline = {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12,
