@@ -199,7 +199,24 @@ def learned_form(args, r, scenes, sids, scene_ids, P, K, W, H, n, out, ms_graph,
     if not args.no_cpu and args.oracle_frames > 0:
         vs_oracle = learned_vs_oracle(args, r, scenes, scene_ids, P, K, W, H, thr, torch)
     net = network_roofline(r, scene_ids, P, K, W, H, n, torch)
+    # where the step's time goes: the low-resolution render of every camera
+    # (graph-replayed, as inside the form), the network, and the rest (the
+    # fallback cameras' full-resolution render, scores, the head)
+    lo_out = r.alloc_outputs(n, W // 4, H // 4, alpha=False)
+    Klo = (K / 4).contiguous()
+
+    def step_lo():
+        r.render(scene_ids, P, Klo, W // 4, H // 4, out=lo_out, use_graph=True)
+
+    step_lo()
+    ms_lo = time_steps(step_lo, args.steps, torch) * 1e3
+    r.drop_graphs()
+    del lo_out
+    parts = {"low_res_render": ms_lo, "network": net["ms"],
+             "fallback_render_and_rest": ms - ms_lo - net["ms"]}
+    log("learned form split (ms/step): " + ", ".join(f"{k} {v:.1f}" for k, v in parts.items()))
     return {"ms_per_step": ms, "frames_per_s": n / ms * 1e3, "speedup_over_batched": ms_graph / ms,
+            "split_ms_per_step": parts,
             "speedup_over_plain": None,
             "fallback_rate": nf / n, "fallback_threshold": thr,
             "psnr_target_met_by_network": bool(pa.size and pa.min() >= args.psnr_target),

@@ -82,6 +82,30 @@ def test_projection_records_match_oracle(gpu_renderer, w0, w1, which):
     # GPU machine contains the oracle's exact box
     assert np.all(got[v, 10] <= ref["x0"][v]) and np.all(got[v, 11] >= ref["x1"][v])
     assert np.all(got[v, 12] <= ref["y0"][v]) and np.all(got[v, 13] >= ref["y1"][v])
+    # What the FP32 projection's errors do to alpha where the skip decision
+    # is taken: on the oracle's alpha = 1/255 contour d^T Q d = r^2,
+    # r^2 = 2 ln(255 o), the GPU's q differs by at most r^2 lambda_max (the
+    # largest |eigenvalue| of Q^-1/2 dQ Q^-1/2) + 2 r |dmu|_Q, and alpha by
+    # half that, relatively. The oracle's skip band (2e-3 of 1/255) must
+    # hold it with room to spare: any pixel the two sides may decide
+    # differently is then flagged.
+    o = ref["opacity"][v]
+    keep = o * 255.0 > 1.0 + 1e-3
+    Qr = np.stack([ref["conic_a"][v], ref["conic_b"][v], ref["conic_b"][v], ref["conic_c"][v]],
+                  -1).reshape(-1, 2, 2)[keep]
+    dQ = (np.stack([got[v, 4], got[v, 5], got[v, 5], got[v, 6]], -1).reshape(-1, 2, 2)[keep]
+          - Qr)
+    dmu = np.stack([got[v, 0] - ref["u"][v], got[v, 1] - ref["v"][v]], -1)[keep]
+    w, U = np.linalg.eigh(Qr)
+    Qih = U @ (np.einsum("ni,nij->nij", 1.0 / np.sqrt(w), np.transpose(U, (0, 2, 1))))
+    lam = np.abs(np.linalg.eigvalsh(Qih @ dQ @ Qih)).max(axis=1)
+    r2 = 2.0 * np.log(255.0 * o[keep])
+    mq = np.sqrt(np.einsum("ni,nij,nj->n", dmu, Qr, dmu))
+    rel_alpha = 0.5 * (r2 * lam + 2.0 * np.sqrt(r2) * mq)
+    print(f"workload {which}: alpha error on the 1/255 contour from the projection: max "
+          f"{rel_alpha.max():.2e}, 99.9th percentile {np.percentile(rel_alpha, 99.9):.2e} "
+          f"(skip band {oracle.DEFAULT_MARGINS[0]:.0e})", flush=True)
+    assert rel_alpha.max() < oracle.DEFAULT_MARGINS[0] / 2
 
 
 # -------------------------------------------------------------- workload 0 --
