@@ -316,3 +316,94 @@ def test_tied_run_beyond_the_bound_is_unresolved():
     assert r.counters["unresolved"] > 0
     rep = oracle.compare(r, r.rgb, r.depth, r.alpha)
     assert rep["failed"] == 0 and rep["unresolved"] == r.counters["unresolved"]
+
+
+# ----------------------------------------------------------- counters ----
+
+def _ellipse_boxes(rec, k=4096):
+    """Bounding boxes of the alpha >= 1/255 ellipses, from points sampled on
+    each ellipse's boundary (delta = r L (cos t, sin t), Sigma' = L L^T,
+    r^2 = 2 ln(o / alpha_min)); NaN where opacity < alpha_min."""
+    t = np.linspace(0.0, 2.0 * np.pi, k, endpoint=False)
+    out = np.full((len(rec["u"]), 4), np.nan)
+    for g in range(len(rec["u"])):
+        o = rec["opacity"][g]
+        if not rec["in_front"][g] or o < AMIN:
+            continue
+        S = np.array([[rec["cov_a"][g], rec["cov_b"][g]], [rec["cov_b"][g], rec["cov_c"][g]]])
+        L = np.linalg.cholesky(S)
+        r = math.sqrt(2.0 * math.log(o / AMIN))
+        pts = r * (L @ np.stack([np.cos(t), np.sin(t)]))
+        out[g] = (rec["u"][g] + pts[0].min(), rec["u"][g] + pts[0].max(),
+                  rec["v"][g] + pts[1].min(), rec["v"][g] + pts[1].max())
+    return out
+
+
+@pytest.mark.parametrize("seed,n,W,H,spread", [(21, 30, 40, 24, 0.9), (22, 60, 48, 40, 0.9),
+                                               (23, 15, 33, 17, 0.9), (24, 80, 40, 30, 4.0)])
+def test_counters_match_brute_force(seed, n, W, H, spread):
+    """The oracle's counters (visible Gaussians, 16x16-tile instances of their
+    exact boxes, contributing pairs), against counts taken independently:
+    boxes from points sampled on each alpha = 1/255 ellipse, and the
+    contributors of every pixel from the product form's included prefix
+    (a per-pixel loop in Python floats over the projection records)."""
+    sc = scenegen.tiny_scene(n, seed, sh_degree=1, spread=spread, log_scale_mean=-2.0)
+    intr = [W * 0.7, W * 0.7, W / 2 + 0.25, H / 2 - 0.35]
+    r = oracle.render(sc, IDENT_POSE, intr, W, H)
+    rec = oracle.project_all(sc, IDENT_POSE, intr, W, H)
+    boxes = _ellipse_boxes(rec)
+    vis = tiles = 0
+    edge = 0
+    for b in boxes:
+        if np.isnan(b[0]):
+            continue
+        # pixel centres i + 1/2 inside [x0, x1], clipped to the image
+        x0 = max(0, math.ceil(b[0] - 0.5)); x1 = min(W - 1, math.floor(b[1] - 0.5))
+        y0 = max(0, math.ceil(b[2] - 0.5)); y1 = min(H - 1, math.floor(b[3] - 0.5))
+        # a box edge within sampling error of a pixel centre may go either way
+        if min(abs((b[j] - 0.5) - round(b[j] - 0.5)) for j in range(4)) < 1e-5:
+            edge += 1
+        if x0 <= x1 and y0 <= y1:
+            vis += 1
+            tiles += (x1 // 16 - x0 // 16 + 1) * (y1 // 16 - y0 // 16 + 1)
+    c = r.counters
+    print(f"visible {c['visible']} / {vis}, instances {c['instances16']} / {tiles}, "
+          f"edge cases {edge}")
+    assert vis > 5
+    if spread > 2:
+        assert vis < n - 5   # some Gaussians project outside the image
+    assert abs(c["visible"] - vis) <= edge
+    assert abs(c["instances16"] - tiles) <= 4 * edge
+    # contributors per pixel: the included prefix of the product form
+    prod = product_form_counts(rec, W, H)
+    n_alt = len(np.unique(r.var_pix))
+    print(f"pairs {c['pairs']} / {prod}, pixels with alternatives {n_alt}")
+    assert abs(c["pairs"] - prod) <= 2 * n_alt, (c["pairs"], prod, n_alt)
+    if n_alt == 0:
+        assert c["pairs"] == prod
+
+
+def product_form_counts(rec, W, H):
+    """Total over pixels of the number of Gaussians in the included prefix
+    (largest k with prod_{j<=k} (1 - a_j) >= T_min over the (z, index)-ordered
+    candidates with a >= 1/255), alpha in FP64 from the projection records."""
+    n = len(rec["u"])
+    total = 0
+    front = [g for g in range(n) if rec["in_front"][g]]
+    order = sorted(front, key=lambda g: (rec["z"][g], g))
+    for j in range(H):
+        for i in range(W):
+            prod = 1.0
+            for g in order:
+                dx = i + 0.5 - rec["u"][g]
+                dy = j + 0.5 - rec["v"][g]
+                q = rec["conic_a"][g] * dx * dx + 2 * rec["conic_b"][g] * dx * dy + \
+                    rec["conic_c"][g] * dy * dy
+                a = min(AMAX, rec["opacity"][g] * math.exp(-q / 2))
+                if a < AMIN:
+                    continue
+                if prod * (1 - a) < TMIN:
+                    break
+                prod *= 1 - a
+                total += 1
+    return total
