@@ -53,7 +53,9 @@ def build(jobs: int = 4, verbose: bool = False) -> str:
             sys.stderr.write(f"--- {s}\n{text}\n")
         raise RuntimeError("hipcc failed for " + ", ".join(s for s, _ in failed))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    rocm_lib = os.path.join(os.path.dirname(os.path.dirname(hipcc)), "lib")
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           f"-L{rocm_lib}", f"-Wl,-rpath,{rocm_lib}", "-lrocprofiler-sdk-roctx"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

@@ -15,6 +15,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/gs.h"
 #include "gs_device.h"
 #include "kernels.h"
@@ -23,6 +25,15 @@
 using namespace gs;
 
 namespace {
+
+// A roctx range for the lifetime of the object (shown by rocprofv3
+// --marker-trace; a no-op when no tool is attached).
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 struct GsError : std::runtime_error {
     int code;
@@ -205,6 +216,8 @@ struct gs_ctx {
     int device = 0;
     int cu_count = 0;
     std::string arch;  // gcnArchName of the device (autotune cache key)
+    bool trace = false;  // GS_TRACE set: one line per render on stderr
+    bool debug = false;  // GS_DEBUG set: eager renders check every stage
     unsigned char *scratch = nullptr;  // this device's copy of the scratch array
     std::string err;
     std::vector<std::unique_ptr<Scene>> scenes;
@@ -507,6 +520,19 @@ void enqueue_status(gs_ctx *ctx, int n_lanes, hipStream_t st)
                        ctx->status_dev.p, ctx->status_host_dev);
 }
 
+// GS_DEBUG: wait for stream s after a stage of an eager render and turn a
+// device error into an error that names the stage (not while capturing).
+void debug_check(gs_ctx *ctx, hipStream_t s, const char *stage)
+{
+    if (!ctx->debug) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess)
+        throw GsError(GS_ERR_HIP, std::string("stage ") + stage + ": " + hipGetErrorString(e));
+}
+
 // Projection, compaction, depth sort, tile emission, tile sort and ranges
 // of one chunk on lane L (stream s); returns which half of the instance
 // ping-pong holds the tile-sorted instances (the depth-sorted records are
@@ -528,23 +554,27 @@ int enqueue_chunk_bins(gs_ctx *ctx, const Plan &P, const Chunk &c, Lane &L, hipS
                            cam_slot, near, P.W, P.H, L.rec.p, L.rect.p,
                            L.zbits.p, L.vis.p, s);
     T.end(GS_STAGE_PROJECT, t0);
+    debug_check(ctx, s, "project");
     // visible count, order-preserving compaction, per-camera segments
     t0 = T.begin();
     compact_visible(L.vis.p, n_words, cam_slot, c.count, L.zbits.p, L.dkeys[0].p,
                     L.dvals[0].p, L.counts.p + 0, L.vis_start.p, scan, s);
     T.end(GS_STAGE_COMPACT, t0);
+    debug_check(ctx, s, "compact");
     // depth sort inside each camera's segment: key = z bits (z > 0)
     t0 = T.begin();
     const int r = seg_sort_u32(L.dkeys[0].p, L.dvals[0].p, L.dkeys[1].p, L.dvals[1].p,
                                L.vis_start.p, c.count, (uint32_t)c.slots, 31, 0u, sort, s,
                                L.rect.p, L.srect.p);
     T.end(GS_STAGE_DEPTH_SORT, t0);
+    debug_check(ctx, s, "depth sort");
     // tile instances in (camera, depth, index) order, keyed by tile
     t0 = T.begin();
     emit_instances(L.dvals[r].p, L.counts.p + 0, (uint32_t)c.slots, L.vis_start.p, c.count,
                    L.srect.p, ch.tw, ch.th, P.tiles_x, cap, L.ikeys[0].p, L.ivals[0].p,
                    L.inst_start.p, L.counts.p, L.flags.p, scan, s);
     T.end(GS_STAGE_EMIT, t0);
+    debug_check(ctx, s, "emit");
     // stable sort by tile inside each camera keeps the depth order in
     // each tile
     const uint64_t n_tiles = (uint64_t)c.count * P.tiles_per_cam;
@@ -556,10 +586,12 @@ int enqueue_chunk_bins(gs_ctx *ctx, const Plan &P, const Chunk &c, Lane &L, hipS
                                 L.inst_start.p, c.count, cap, tbits, (uint32_t)P.tiles_per_cam,
                                 sort, s);
     T.end(GS_STAGE_TILE_SORT, t0);
+    debug_check(ctx, s, "tile sort");
     t0 = T.begin();
     launch_zero_u32((uint32_t *)L.ranges.p, n_tiles * 2, s);
     launch_ranges(L.ikeys[r2].p, L.counts.p + 2, L.ranges.p, cap, s);
     T.end(GS_STAGE_RANGES, t0);
+    debug_check(ctx, s, "ranges");
     if (depth_half) *depth_half = r;
     return r2;
 }
@@ -618,6 +650,7 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
         launch_raster(ch.tw, ch.th, ch.batch, ch.persistent != 0, a, c.count, L.queue.p,
                       persistent_blocks, count_pairs ? L.flags.p : nullptr, s);
         T.end(GS_STAGE_RASTER, t0);
+        debug_check(ctx, s, "raster");
     }
     for (int l = 1; l < n_lanes; ++l) {
         HIP_CHECK(hipEventRecord(ctx->ev_join[l - 1], aux[l - 1]));
@@ -763,11 +796,14 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
                       ctx->sized.count(config) == 0;
     ctx->last = gs_stats{};
     int regrows = 0;
+    size_t n_chunks = 0;
+    bool captured = false;
     for (int attempt = 0; attempt < 6; ++attempt) {
         StageTimer timer{ctx, st, o.timing != 0};
         if (!use_graph) {
             // eager: the plain form is the same kernel sequence with one camera per chunk
             std::unique_ptr<Plan> P = make_plan(ctx, n_cams, scene_ids, W, H, ch, subset);
+            n_chunks = P->chunks.size();
             if (ensure_workspace(ctx, *P, n_lanes)) clear_graphs(ctx);
             enqueue_render(ctx, *P, poses, intr, o.near_plane, o.bg, rgb, depth, alpha, st,
                            ctx->aux_stream, n_lanes, &timer, o.count_pairs != 0, blend);
@@ -778,6 +814,8 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
                               tail;
             auto it = ctx->graphs.find(key);
             if (it == ctx->graphs.end()) {
+                TraceRange tr("gs capture");
+                captured = true;
                 auto g = std::make_unique<GraphEntry>();
                 g->plan = make_plan(ctx, n_cams, scene_ids, W, H, ch, subset);
                 if (ensure_workspace(ctx, *g->plan, n_lanes)) {
@@ -805,6 +843,7 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
                 ++ctx->graph_captures;
                 it = ctx->graphs.emplace(key, std::move(g)).first;
             }
+            n_chunks = it->second->plan->chunks.size();
             HIP_CHECK(hipGraphLaunch(it->second->exec, st));
         }
         HIP_CHECK(hipEventRecord(ctx->ev_done, st));
@@ -839,6 +878,14 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
     ctx->last.chunk_cams = ch.chunk;
     ctx->last.persistent = ch.persistent;
     ctx->last_deferred = !wait;
+    if (ctx->trace)
+        fprintf(stderr,
+                "[gs] render: %d cameras %dx%d, choice %s, %zu chunks on %d pipelines, %s%s, "
+                "%s, instance capacity %llu, regrows %d\n",
+                n_render, W, H, choice_key(ch).c_str(), n_chunks, n_lanes,
+                use_graph ? (captured ? "graph captured" : "graph replayed") : "eager",
+                batched ? "" : " (plain)", wait ? "waited" : "returned before finishing",
+                (unsigned long long)ctx->inst_cap, regrows);
     return GS_OK;
 }
 
@@ -1235,6 +1282,9 @@ int gs_create(int hip_device, gs_ctx **out)
         HIP_CHECK(hipGetDeviceProperties(&prop, hip_device));
         ctx->cu_count = prop.multiProcessorCount;
         ctx->arch = prop.gcnArchName;
+        const char *tr = std::getenv("GS_TRACE"), *dbg = std::getenv("GS_DEBUG");
+        ctx->trace = tr && *tr && std::strcmp(tr, "0") != 0;
+        ctx->debug = dbg && *dbg && std::strcmp(dbg, "0") != 0;
         {
             constexpr uint64_t kSlotBytes = 84;
             const uint64_t b = (uint64_t)prop.totalGlobalMem / (3 * kLanes * kSlotBytes);
@@ -1445,6 +1495,7 @@ int gs_render_batch(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const
                     const float *intrinsics, int32_t width, int32_t height, float *rgb,
                     float *depth, float *alpha, const gs_render_opts *opts, void *stream)
 {
+    TraceRange trace_range("gs_render_batch");
     int rc = validate_render_args(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb,
                                   depth);
     if (rc) return rc;
@@ -1467,6 +1518,7 @@ int gs_render_backward(gs_ctx *ctx, int32_t scene_id, int32_t n_cams, const floa
                        const gs_render_opts *opts, float *d_means, float *d_scales,
                        float *d_quats, float *d_opacity, float *d_sh, void *stream)
 {
+    TraceRange trace_range("gs_render_backward");
     if (!ctx) return GS_ERR_INVALID_ARG;
     if (scene_id < 0 || scene_id >= (int)ctx->scenes.size() || !ctx->scenes[scene_id])
         return fail(ctx, GS_ERR_INVALID_ARG, "no such scene");
@@ -1495,6 +1547,7 @@ int gs_render_due(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const f
                   int32_t period, const int32_t *phase, float *rgb, float *depth, float *alpha,
                   const gs_render_opts *opts, int32_t *n_due_out, void *stream)
 {
+    TraceRange trace_range("gs_render_due");
     int rc = validate_render_args(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb,
                                   depth);
     if (rc) return rc;
@@ -1531,6 +1584,7 @@ int gs_render_batch_motion_blur(gs_ctx *ctx, int32_t n_cams, const int32_t *scen
                                 float shutter, int32_t n_sub, float *rgb, float *depth,
                                 float *alpha, const gs_render_opts *opts, void *stream)
 {
+    TraceRange trace_range("gs_render_batch_motion_blur");
     int rc = validate_render_args(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb,
                                   depth);
     if (rc) return rc;
@@ -1771,6 +1825,7 @@ int gs_autotune(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
                 const float *intrinsics, int32_t width, int32_t height, float *rgb, float *depth,
                 const char *cache_path, void *stream)
 {
+    TraceRange trace_range("gs_autotune");
     int rc = validate_render_args(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb,
                                   depth);
     if (rc) return rc;
@@ -2183,6 +2238,7 @@ int gs_upsampler_train(gs_ctx *ctx, const gs_train_opts *opts, int32_t n_pairs,
                        const int32_t *scene_ids, const float *poses, const float *intrinsics,
                        int32_t width, int32_t height, float *loss_curve, void *stream)
 {
+    TraceRange trace_range("gs_upsampler_train");
     if (!ctx) return GS_ERR_INVALID_ARG;
     if (!opts || !scene_ids || !poses || !intrinsics || n_pairs < 1 || width % 4 || height % 4 ||
         width < 4 || height < 4)
@@ -2231,6 +2287,7 @@ int gs_render_batch_upsampled(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_
                               float fallback_threshold, int32_t *n_fallback_out,
                               const gs_render_opts *opts, void *stream)
 {
+    TraceRange trace_range("gs_render_batch_upsampled");
     int rc = validate_render_args(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb,
                                   depth);
     if (rc) return rc;

@@ -567,3 +567,29 @@ def test_pair_and_visibility_counters_match_oracle(gpu_renderer, w0, w1):
         assert rc["instances16"] <= st["instances"] <= rc["instances16"] * 1.01 + 3
         assert st["pairs_evaluated"] >= st["pairs_contrib"]
         assert st["pairs_issued"] >= st["pairs_evaluated"]
+
+
+def test_trace_and_debug_modes(gpu_renderer, w0, capfd, monkeypatch):
+    """GS_TRACE prints one line per render on stderr; GS_DEBUG waits after
+    every stage of an eager render and checks for device errors. Neither
+    changes a pixel."""
+    import paper_2510_15352_amd as gs
+    sc, sid, cams = w0
+    ref = [_np(t) for t in gpu_renderer.render([sid], cams["poses"], cams["intrinsics"], 64, 48)]
+    monkeypatch.setenv("GS_TRACE", "1")
+    monkeypatch.setenv("GS_DEBUG", "1")
+    r = gs.Renderer(0)
+    try:
+        s2 = r.upload_scene(sc)
+        for use_graph in (False, True, True):
+            got = r.render([s2] * 3, np.repeat(cams["poses"], 3, 0),
+                           np.repeat(cams["intrinsics"], 3, 0), 64, 48, use_graph=use_graph)
+            for x, y in zip(ref, got):
+                assert np.array_equal(x, _np(y[1]))
+        err = capfd.readouterr().err
+        lines = [l for l in err.splitlines() if l.startswith("[gs] render:")]
+        print("\n".join(lines))
+        assert len(lines) == 3
+        assert "eager" in lines[0] and "graph captured" in lines[1] and "graph replayed" in lines[2]
+    finally:
+        r.close()
