@@ -585,7 +585,7 @@ def test_trace_and_debug_modes(gpu_renderer, w0, capfd, monkeypatch):
             got = r.render([s2] * 3, np.repeat(cams["poses"], 3, 0),
                            np.repeat(cams["intrinsics"], 3, 0), 64, 48, use_graph=use_graph)
             for x, y in zip(ref, got):
-                assert np.array_equal(x, _np(y[1]))
+                assert np.array_equal(x[0], _np(y[1]))
         err = capfd.readouterr().err
         lines = [l for l in err.splitlines() if l.startswith("[gs] render:")]
         print("\n".join(lines))
