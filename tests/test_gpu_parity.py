@@ -581,9 +581,11 @@ def test_trace_and_debug_modes(gpu_renderer, w0, capfd, monkeypatch):
     r = gs.Renderer(0)
     try:
         s2 = r.upload_scene(sc)
+        out = r.alloc_outputs(3, 64, 48)
         for use_graph in (False, True, True):
             got = r.render([s2] * 3, np.repeat(cams["poses"], 3, 0),
-                           np.repeat(cams["intrinsics"], 3, 0), 64, 48, use_graph=use_graph)
+                           np.repeat(cams["intrinsics"], 3, 0), 64, 48, out=out,
+                           use_graph=use_graph)
             for x, y in zip(ref, got):
                 assert np.array_equal(x[0], _np(y[1]))
         err = capfd.readouterr().err
