@@ -5,6 +5,8 @@ Tolerance (the renderer's stated bar): max-abs RGB 2e-3, relative depth
 match an alternative the oracle lists for decisions sitting at a threshold
 within rounding (oracle.compare).
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -595,3 +597,50 @@ def test_trace_and_debug_modes(gpu_renderer, w0, capfd, monkeypatch):
         assert "eager" in lines[0] and "graph captured" in lines[1] and "graph replayed" in lines[2]
     finally:
         r.close()
+
+
+def test_extreme_gaussians_and_off_centre_principal_point(gpu_renderer):
+    """Degenerate and extreme splats against the oracle: opacity exactly 1
+    (alpha clamped to 0.99 at the centre), exactly fl32(1/255), just below it
+    and 0; a Gaussian much larger than the view (the tangent clamp of the
+    Jacobian); needles (one long axis, two of 1e-4 m) along the image
+    diagonal and along the optical axis; sub-pixel Gaussians (1e-5 m: the
+    0.3 px^2 low-pass sets their footprint); a Gaussian right at the near
+    plane; with the principal point far off the image centre (asymmetric
+    tangent clamp) and on it."""
+    rng = np.random.default_rng(77)
+    n_rand = 60
+    sc = scenegen.tiny_scene(n_rand, 78, sh_degree=2, spread=0.7)
+    special = []   # (mean, scales, quat, opacity)
+    amin = float(np.float32(1.0 / 255.0))
+    for o in (1.0, amin, float(np.nextafter(np.float32(amin), np.float32(0))), 0.0):
+        special.append(((rng.uniform(-0.4, 0.4), rng.uniform(-0.3, 0.3), 2.5), (0.05, 0.03, 0.04),
+                        (1.0, 0.0, 0.0, 0.0), o))
+    special.append(((0.1, -0.1, 3.0), (12.0, 9.0, 10.0), (0.9, 0.1, 0.3, 0.2), 0.6))
+    c, s_ = math.cos(math.pi / 8), math.sin(math.pi / 8)
+    special.append(((0.0, 0.0, 2.8), (0.6, 1e-4, 1e-4), (c, 0.0, 0.0, s_), 0.9))   # diagonal
+    special.append(((0.2, 0.1, 2.2), (1e-4, 1e-4, 0.8), (1.0, 0.0, 0.0, 0.0), 0.95))  # on axis
+    for k in range(6):
+        special.append(((rng.uniform(-0.5, 0.5), rng.uniform(-0.4, 0.4), rng.uniform(2, 4)),
+                        (1e-5, 1e-5, 1e-5), (1.0, 0.0, 0.0, 0.0), 0.9))
+    special.append(((0.05, 0.02, 0.2 + 2e-5), (0.05, 0.05, 0.05), (1.0, 0.0, 0.0, 0.0), 0.7))
+    m = len(special)
+    sc2 = dict(sh_degree=2)
+    sc2["means"] = np.concatenate([sc["means"], np.array([s[0] for s in special])]).astype(np.float32)
+    sc2["scales"] = np.concatenate([sc["scales"], np.array([s[1] for s in special])]).astype(np.float32)
+    sc2["quats"] = np.concatenate([sc["quats"], np.array([s[2] for s in special])]).astype(np.float32)
+    sc2["opacity"] = np.concatenate([sc["opacity"], np.array([s[3] for s in special])]).astype(np.float32)
+    sc2["sh"] = np.concatenate([sc["sh"], rng.normal(0, 0.3, size=(m, 9, 3))]).astype(np.float32)
+    assert float(sc2["opacity"][n_rand + 1]) == amin
+    sid = gpu_renderer.upload_scene(sc2)
+    try:
+        pose = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1).astype(np.float32)
+        poses = np.stack([pose, pose, pose])
+        intr = np.array([[50.0, 50.0, 32.0, 24.0], [60.0, 45.0, 6.5, 41.0],
+                         [40.0, 40.0, 58.0, 3.0]], np.float32)
+        rgb, depth, alpha = gpu_renderer.render([sid] * 3, poses, intr, 64, 48)
+        for k in range(3):
+            ref = oracle.render(sc2, poses[k], intr[k], 64, 48)
+            _check(ref, _np(rgb[k]), _np(depth[k]), _np(alpha[k]), f"extreme cam {k}")
+    finally:
+        gpu_renderer.release_scene(sid)
