@@ -177,11 +177,15 @@ def learned_form(args, r, scenes, sids, scene_ids, P, K, W, H, n, out, ms_graph,
     uo = (torch.empty_like(out[0]), torch.empty_like(out[1]), None)
 
     def step_learned():
-        return r.render_upsampled(scene_ids, P, K, W, H, threshold=thr, out=uo)
+        # asynchronous: the fallback cameras are chosen on the device
+        return r.render_upsampled(scene_ids, P, K, W, H, threshold=thr, out=uo,
+                                  count_fallback=False)
 
     step_learned()
     ms = time_steps(step_learned, args.steps, torch) * 1e3
-    rgb_u, depth_u, score_u, nf = step_learned()
+    r.status()   # raises if a timed render overflowed its instance buffers
+    rgb_u, depth_u, score_u, nf = r.render_upsampled(scene_ids, P, K, W, H, threshold=thr,
+                                                     out=uo)
     psnr_e = r.frame_psnr(rgb_u, out[0]).cpu().numpy()
     acc = ~(score_u.cpu().numpy() > thr)   # frames the network's output was kept for
     pa = psnr_e[acc]

@@ -430,7 +430,15 @@ int gs_upsampler_train(gs_ctx *ctx, const gs_train_opts *opts, int32_t n_pairs,
  * RGB + depth/10) exceeds fallback_threshold is rendered again at full
  * resolution into the same output slots. score_out (DEVICE [n], nullable)
  * receives the scores, *n_fallback_out (HOST, nullable) the number of
- * re-rendered cameras. width and height must be multiples of 4. */
+ * re-rendered cameras. width and height must be multiples of 4.
+ * The cameras to re-render are chosen on the device: the full-resolution
+ * render covers the whole batch under a per-camera mask, and a masked camera
+ * projects no Gaussian and keeps the network's frame. With n_fallback_out
+ * null the call is asynchronous on stream, like gs_render_batch (its two
+ * renders follow the same first-render and capacity rules, and
+ * gs_render_status reports their overflows); with it set the call waits for
+ * the count. gs_last_stats afterwards describes the full-resolution
+ * render. */
 int gs_render_batch_upsampled(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids,
                               const float *poses, const float *intrinsics, int32_t width,
                               int32_t height, float *rgb, float *depth, float *score_out,

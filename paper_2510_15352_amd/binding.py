@@ -517,8 +517,11 @@ class Renderer:
         return curve
 
     def render_upsampled(self, scene_ids, poses, intrinsics, width, height, threshold=float("inf"),
-                         out=None, opts=None, **kw):
-        """Upsampled render; returns (rgb, depth, score, n_fallback)."""
+                         out=None, opts=None, count_fallback=True, **kw):
+        """Upsampled render; returns (rgb, depth, score, n_fallback).
+
+        With count_fallback=False the call returns before the GPU finishes
+        and n_fallback is None (counting the re-rendered cameras waits)."""
         torch = self.torch
         sids = np.ascontiguousarray(np.asarray(scene_ids, dtype=np.int32).reshape(-1))
         n = len(sids)
@@ -531,9 +534,9 @@ class Renderer:
         o = opts if opts is not None else self.opts(**kw)
         self._check(self.lib.gs_render_batch_upsampled(
             self.ctx, n, sids.ctypes.data, P.data_ptr(), K.data_ptr(), int(width), int(height),
-            rgb.data_ptr(), depth.data_ptr(), score.data_ptr(), float(threshold), ctypes.byref(nf),
-            ctypes.byref(o), _stream_ptr(torch)))
-        return rgb, depth, score, int(nf.value)
+            rgb.data_ptr(), depth.data_ptr(), score.data_ptr(), float(threshold),
+            ctypes.byref(nf) if count_fallback else None, ctypes.byref(o), _stream_ptr(torch)))
+        return rgb, depth, score, (int(nf.value) if count_fallback else None)
 
     def frame_psnr(self, a, b):
         torch = self.torch

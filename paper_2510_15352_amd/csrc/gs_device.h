@@ -32,7 +32,8 @@ struct CamParams {
     float fx, fy, cx, cy;
     float lxn, lxp, lyn, lyp;  // clamped tangent range of x/z and y/z
     float kx, ky;              // sqrt(1 + max clamped tangent^2): bounds |row of J| z / f
-    float pad[7];
+    float active;              // 1: render this camera; 0: it sees nothing (masked out)
+    float pad[6];
 };
 static_assert(sizeof(CamParams) == 32 * 4, "CamParams is 128 B");
 

@@ -58,7 +58,7 @@ __global__ void k_scene_prep(const float *__restrict__ means, const float *__res
 // tangent clamp range 1.3x the image half-extent on each side.
 __global__ void k_camera_setup(const float *__restrict__ poses, const float *__restrict__ intr,
                                const int32_t *__restrict__ cam_global, int n_cams, int W, int H,
-                               CamParams *__restrict__ out)
+                               const uint32_t *__restrict__ mask, CamParams *__restrict__ out)
 {
     const int cl = blockIdx.x * blockDim.x + threadIdx.x;
     if (cl >= n_cams) return;
@@ -79,7 +79,8 @@ __global__ void k_camera_setup(const float *__restrict__ poses, const float *__r
     c.lyp = kTanClamp * ((float)H - c.cy) / c.fy;
     c.kx = sqrtf(1.0f + fmaxf(c.lxn * c.lxn, c.lxp * c.lxp));
     c.ky = sqrtf(1.0f + fmaxf(c.lyn * c.lyn, c.lyp * c.lyp));
-    for (int k = 0; k < 7; ++k) c.pad[k] = 0.0f;
+    c.active = (mask == nullptr || mask[cg] != 0u) ? 1.0f : 0.0f;
+    for (int k = 0; k < 6; ++k) c.pad[k] = 0.0f;
     out[cl] = c;
 }
 
@@ -117,7 +118,10 @@ __global__ __launch_bounds__(256) void k_project(
     float4 po = make_float4(0.f, 0.f, 0.f, 0.f), a = po, b = po;
     float2 m8r = make_float2(0.f, 0.f);
     float k[NC * 3];
-    if (in_range) {
+    // a block whose cameras are all masked out loads no Gaussian
+    bool any_active = false;
+    for (int ci = 0; ci < it.ncam; ++ci) any_active |= cams[it.cam0 + ci].active > 0.0f;
+    if (in_range && any_active) {
         po = sc.pos_op[g];
         a = sc.m01[g];
         b = sc.m23[g];
@@ -132,7 +136,8 @@ __global__ __launch_bounds__(256) void k_project(
     for (int ci = 0; ci < it.ncam; ++ci) {
         const CamParams &cam = s_cam[ci];
         Projected P;
-        bool visible = in_range && project_gaussian(cam, po, a, b, m8r, near, W, H, P);
+        bool visible = in_range && cam.active > 0.0f &&
+                       project_gaussian(cam, po, a, b, m8r, near, W, H, P);
         const uint32_t slot = s_slot[ci] + (uint32_t)g;
         if (visible) {
             float dx = po.x - cam.C[0], dy = po.y - cam.C[1], dz = po.z - cam.C[2];
@@ -204,11 +209,12 @@ void launch_scene_prep(const float *means, const float *scales, const float *qua
 }
 
 void launch_camera_setup(const float *poses, const float *intr, const int32_t *cam_global,
-                         int n_cams, int W, int H, CamParams *out, hipStream_t st)
+                         int n_cams, int W, int H, CamParams *out, hipStream_t st,
+                         const uint32_t *mask)
 {
     const int bs = 64;
     hipLaunchKernelGGL(k_camera_setup, dim3((n_cams + bs - 1) / bs), dim3(bs), 0, st, poses,
-                       intr, cam_global, n_cams, W, H, out);
+                       intr, cam_global, n_cams, W, H, mask, out);
 }
 
 void launch_project(int deg, const ProjItem *items, int n_items, const SceneDev *scenes,

@@ -76,6 +76,8 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
     static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are made of 8x8 wave blocks");
     static_assert(B % 64 == 0, "batches are whole sets of 64 records");
     constexpr int SX = TW / 8;
+    // a masked-out camera keeps its frame (block-uniform test, before any work)
+    if (a.cam_mask && a.cam_mask[a.cam_global[cl]] == 0u) return;
     // wave-uniform: kept in scalar registers with everything derived from it
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const uint32_t lane = __lane_id();

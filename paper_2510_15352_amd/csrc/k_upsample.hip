@@ -703,6 +703,27 @@ void launch_up_score(const float *x0f, int n, int h, int w, float *score, hipStr
     hipLaunchKernelGGL(k_up_score, dim3(n), dim3(256), 0, st, x0f, h, w, score);
 }
 
+// Fallback flags of the upsampled form: mask[i] = 1 when camera i's score is
+// not at most the threshold (NaN scores are flagged), and *count (zeroed by
+// the caller) gains the number of flagged cameras.
+__global__ __launch_bounds__(256) void k_up_flag(const float *__restrict__ score, int n, float thr,
+                                                 uint32_t *__restrict__ mask,
+                                                 uint32_t *__restrict__ count)
+{
+    const int i = blockIdx.x * 256 + (int)threadIdx.x;
+    const bool f = i < n && !(score[i] <= thr);
+    if (i < n) mask[i] = f ? 1u : 0u;
+    const uint64_t b = __ballot(f);
+    if (__lane_id() == 0 && b) atomicAdd(count, (uint32_t)__popcll(b));
+}
+
+void launch_up_flag(const float *score, int n, float thr, uint32_t *mask, uint32_t *count,
+                    hipStream_t st)
+{
+    hipLaunchKernelGGL(k_up_flag, dim3((n + 255) / 256), dim3(256), 0, st, score, n, thr, mask,
+                       count);
+}
+
 void launch_frame_psnr(const float *a, const float *b, int n, int64_t npix, float *out,
                        hipStream_t st)
 {

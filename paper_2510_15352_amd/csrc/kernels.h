@@ -49,6 +49,7 @@ struct RasterArgs {
     const uint32_t *ivals; // tile-sorted instance values (record slots)
     const float4 *rec;          // 48-byte records by slot: A, B, C
     const int32_t *cam_global;  // chunk-local -> batch camera index
+    const uint32_t *cam_mask;   // batch order, nullable: frames of cameras with 0 are not written
     int tiles_x, tiles_per_cam, W, H;
     float bg_r, bg_g, bg_b;
     float *rgb, *depth, *alpha;
@@ -119,8 +120,11 @@ void launch_scene_prep(const float *means, const float *scales, const float *qua
                        const float *opacity, const float *sh, int64_t n, int ncoef, float4 *pos_op,
                        float4 *m01, float4 *m23, float2 *m8r, float *sh_planar, float4 *quat,
                        float4 *scale, int *bad, hipStream_t st);
+// mask (nullable, batch order): cameras whose entry is 0 see nothing and
+// their frames are left as they are.
 void launch_camera_setup(const float *poses, const float *intr, const int32_t *cam_global,
-                         int n_cams, int W, int H, CamParams *out, hipStream_t st);
+                         int n_cams, int W, int H, CamParams *out, hipStream_t st,
+                         const uint32_t *mask = nullptr);
 void launch_project(int deg, const ProjItem *items, int n_items, const SceneDev *scenes,
                     const CamParams *cams, const uint32_t *cam_slot, float near, int W, int H,
                     float4 *rec, uint2 *rect, uint32_t *zbits,

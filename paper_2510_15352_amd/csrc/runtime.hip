@@ -192,6 +192,8 @@ struct Upsampler {
     DevBuf<uint16_t> x0b, a1, a2, a3, dy4, da3, da2, da1;
     // renders used by training and the upsampled form
     DevBuf<float> lo_rgb, lo_depth, hi_rgb, hi_depth, intr_lo, score;
+    // fallback flags of the upsampled form (one per camera) and their count
+    DevBuf<uint32_t> flags, n_flagged;
 };
 
 // Scratch of gs_upsampler_forward_noalloc: the FP32 four-channel input and
@@ -604,7 +606,8 @@ int enqueue_chunk_bins(gs_ctx *ctx, const Plan &P, const Chunk &c, Lane &L, hipS
 void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float *intr, float near,
                     const float bg[3], float *rgb, float *depth, float *alpha, hipStream_t st,
                     const hipStream_t *aux, int n_lanes, StageTimer *tm = nullptr,
-                    bool count_pairs = false, Blend blend = Blend{})
+                    bool count_pairs = false, Blend blend = Blend{},
+                    const uint32_t *cam_mask = nullptr)
 {
     StageTimer off{ctx, st, false};
     StageTimer &T = tm ? *tm : off;
@@ -613,7 +616,7 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
     size_t t0 = T.begin();
     for (int l = 0; l < n_lanes; ++l)
         launch_zero_u32((uint32_t *)ctx->lanes[l].flags.p, sizeof(DevFlags) / 4, st);
-    launch_camera_setup(poses, intr, P.d_order.p, P.n_cams, P.W, P.H, ctx->cams.p, st);
+    launch_camera_setup(poses, intr, P.d_order.p, P.n_cams, P.W, P.H, ctx->cams.p, st, cam_mask);
     T.end(GS_STAGE_SETUP, t0);
     if (n_lanes > 1) {
         HIP_CHECK(hipEventRecord(ctx->ev_fork, st));
@@ -634,6 +637,7 @@ void enqueue_render(gs_ctx *ctx, const Plan &P, const float *poses, const float 
         a.ivals = L.ivals[r2].p;
         a.rec = L.rec.p;
         a.cam_global = P.d_order.p + c.start;
+        a.cam_mask = cam_mask;
         a.tiles_x = P.tiles_x;
         a.tiles_per_cam = P.tiles_per_cam;
         a.W = P.W;
@@ -768,7 +772,7 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
                 const float *intr, int32_t W, int32_t H, float *rgb, float *depth, float *alpha,
                 const gs_render_opts &o, hipStream_t st, const Choice *forced,
                 const std::vector<int32_t> *subset = nullptr, Blend blend = Blend{},
-                bool may_defer = false)
+                bool may_defer = false, const uint32_t *cam_mask = nullptr)
 {
     uint64_t total = 0;
     int rc = check_scene_ids(ctx, n_cams, scene_ids, &total);
@@ -787,8 +791,10 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
         (batched && !o.timing) ? (o.streams > 0 ? std::min<int>(o.streams, kLanes) : kLanes) : 1;
     sync_scene_table(ctx);
     poll_status(ctx);
+    char mask_key[32];
+    snprintf(mask_key, sizeof mask_key, "|m%p", (const void *)cam_mask);
     const std::string tail = "|l" + std::to_string(n_lanes) + "|b" +
-                             std::to_string(blend.mode) + ":" + std::to_string(blend.w);
+                             std::to_string(blend.mode) + ":" + std::to_string(blend.w) + mask_key;
     // the configuration without buffer addresses: the first render of it waits
     const std::string config = graph_key(n_cams, scene_ids, W, H, ch, o.near_plane, o.bg, nullptr,
                                          nullptr, nullptr, nullptr, nullptr, 0, 0, subset) + tail;
@@ -806,7 +812,7 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
             n_chunks = P->chunks.size();
             if (ensure_workspace(ctx, *P, n_lanes)) clear_graphs(ctx);
             enqueue_render(ctx, *P, poses, intr, o.near_plane, o.bg, rgb, depth, alpha, st,
-                           ctx->aux_stream, n_lanes, &timer, o.count_pairs != 0, blend);
+                           ctx->aux_stream, n_lanes, &timer, o.count_pairs != 0, blend, cam_mask);
         } else {
             std::string key = graph_key(n_cams, scene_ids, W, H, ch, o.near_plane, o.bg, poses,
                                         intr, rgb, depth, alpha, ctx->generation, ctx->inst_cap,
@@ -829,7 +835,7 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
                 try {
                     enqueue_render(ctx, *g->plan, poses, intr, o.near_plane, o.bg, rgb, depth,
                                    alpha, ctx->capture_stream, ctx->capture_aux, n_lanes, nullptr,
-                                   false, blend);
+                                   false, blend, cam_mask);
                 } catch (...) {
                     hipGraph_t junk = nullptr;
                     (void)hipStreamEndCapture(ctx->capture_stream, &junk);
@@ -2306,11 +2312,12 @@ int gs_render_batch_upsampled(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_
         U.lo_depth.reserve((size_t)n_cams * lp);
         U.intr_lo.reserve((size_t)n_cams * 4);
         U.score.reserve((size_t)n_cams);
+        U.flags.reserve((size_t)n_cams);
+        U.n_flagged.reserve(1);
         launch_quarter_intr(intrinsics, n_cams, U.intr_lo.p, st);
         int r = render_impl(ctx, n_cams, scene_ids, poses, U.intr_lo.p, w, h, U.lo_rgb.p,
-                            U.lo_depth.p, nullptr, o, st, nullptr);
+                            U.lo_depth.p, nullptr, o, st, nullptr, nullptr, Blend{}, true);
         if (r) return r;
-        const gs_stats lo_stats = ctx->last;
         if (!U.packed) up_pack(ctx, st);
         for (int c0 = 0; c0 < n_cams; c0 += kUpChunk) {
             const int m = std::min(kUpChunk, n_cams - c0);
@@ -2323,24 +2330,21 @@ int gs_render_batch_upsampled(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_
         if (score_out)
             HIP_CHECK(hipMemcpyAsync(score_out, U.score.p, (size_t)n_cams * 4,
                                      hipMemcpyDeviceToDevice, st));
-        // fallback: cameras whose score exceeds the threshold, rendered at full resolution
-        std::vector<float> sc(n_cams);
-        HIP_CHECK(hipMemcpyAsync(sc.data(), U.score.p, (size_t)n_cams * 4, hipMemcpyDeviceToHost, st));
-        HIP_CHECK(hipStreamSynchronize(st));
-        std::vector<int32_t> list;
-        for (int i = 0; i < n_cams; ++i)
-            if (!(sc[i] <= fallback_threshold)) list.push_back(i);
-        const int nf = (int)list.size();
-        // the flagged cameras only, rendered straight into their frames of
-        // the batch outputs (over the network's images)
-        if (nf > 0) {
-            r = render_impl(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb, depth,
-                            nullptr, o, st, nullptr, &list);
-            if (r) return r;
+        // fallback: the cameras whose score exceeds the threshold are flagged
+        // on the device and rendered at full resolution straight into their
+        // frames of the batch outputs (over the network's images); the
+        // render of the others projects nothing and writes nothing
+        launch_zero_u32(U.n_flagged.p, 1, st);
+        launch_up_flag(U.score.p, n_cams, fallback_threshold, U.flags.p, U.n_flagged.p, st);
+        r = render_impl(ctx, n_cams, scene_ids, poses, intrinsics, width, height, rgb, depth,
+                        nullptr, o, st, nullptr, nullptr, Blend{}, true, U.flags.p);
+        if (r) return r;
+        if (n_fallback_out) {
+            uint32_t nf = 0;
+            HIP_CHECK(hipMemcpyAsync(&nf, U.n_flagged.p, 4, hipMemcpyDeviceToHost, st));
+            HIP_CHECK(hipStreamSynchronize(st));
+            *n_fallback_out = (int32_t)nf;
         }
-        HIP_CHECK(hipStreamSynchronize(st));
-        ctx->last = lo_stats;
-        if (n_fallback_out) *n_fallback_out = nf;
         return GS_OK;
     });
 }

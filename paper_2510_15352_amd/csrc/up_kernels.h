@@ -37,6 +37,8 @@ void launch_pack_weights(const float *w, int cout, int cin, int cinp, uint16_t *
 void launch_adam(float *p, float *m, float *v, const float *g, int n, float lr, int step,
                  hipStream_t st);
 void launch_up_score(const float *x0f, int n, int h, int w, float *score, hipStream_t st);
+void launch_up_flag(const float *score, int n, float thr, uint32_t *mask, uint32_t *count,
+                    hipStream_t st);
 void launch_frame_psnr(const float *a, const float *b, int n, int64_t npix, float *out,
                        hipStream_t st);
 void launch_quarter_intr(const float *in, int n, float *out, hipStream_t st);

@@ -136,6 +136,18 @@ def test_training_lowers_loss_and_fallback_paths(gpu_renderer):
     for c in range(8):
         ref_rgb, ref_d = (full[0][c], full[1][c]) if flagged[c] else (rgb[c], depth[c])
         assert bool((rgb2[c] == ref_rgb).all()) and bool((depth2[c] == ref_d).all()), c
+    # asynchronous form (no count asked): two calls enqueued back to back
+    # into their own buffers with different thresholds, then a replay of the
+    # first; one wait at the end, every frame as above
+    bufs = [gpu_renderer.alloc_outputs(8, 640, 480, alpha=False) for _ in range(2)]
+    for k, t in ((0, thr), (1, -1.0), (0, thr)):
+        r = gpu_renderer.render_upsampled(ids, P, K, 640, 480, threshold=t, out=bufs[k],
+                                          count_fallback=False)
+        assert r[3] is None
+    torch.cuda.synchronize()
+    assert bool((bufs[0][0] == rgb2).all()) and bool((bufs[0][1] == depth2).all())
+    assert bool((bufs[1][0] == full[0]).all()) and bool((bufs[1][1] == full[1]).all())
+    gpu_renderer.status()
     gpu_renderer.release_scene(sid)
 
 
