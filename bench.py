@@ -54,6 +54,11 @@ RASTER_SOURCES = ("paper_2510_15352_amd/csrc/k_raster.hip", "paper_2510_15352_am
 TRAFFIC_PROFILE = "profiles/k_raster_workload2_hbm_traffic.md"
 
 
+def gs_error():
+    import paper_2510_15352_amd as gs
+    return gs.GsError
+
+
 def raster_source_digest():
     import hashlib
     h = hashlib.sha256()
@@ -183,7 +188,12 @@ def learned_form(args, r, scenes, sids, scene_ids, P, K, W, H, n, out, ms_graph,
 
     step_learned()
     ms = time_steps(step_learned, args.steps, torch) * 1e3
-    r.status()   # raises if a timed render overflowed its instance buffers
+    overflowed = False
+    try:
+        r.status()   # raises if a timed render overflowed its instance buffers
+    except gs_error() as e:
+        overflowed = True
+        log(f"learned form: a timed render overflowed its instance buffers ({e})")
     rgb_u, depth_u, score_u, nf = r.render_upsampled(scene_ids, P, K, W, H, threshold=thr,
                                                      out=uo)
     psnr_e = r.frame_psnr(rgb_u, out[0]).cpu().numpy()
@@ -223,6 +233,7 @@ def learned_form(args, r, scenes, sids, scene_ids, P, K, W, H, n, out, ms_graph,
             "split_ms_per_step": parts,
             "speedup_over_plain": None,
             "fallback_rate": nf / n, "fallback_threshold": thr,
+            "timed_render_overflowed": overflowed,
             "psnr_target_met_by_network": bool(pa.size and pa.min() >= args.psnr_target),
             "upsampled_frames_psnr_db": {
                 "frames": int(acc.sum()),
