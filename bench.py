@@ -209,10 +209,11 @@ def learned_form(args, r, scenes, sids, scene_ids, P, K, W, H, n, out, ms_graph,
         curve_thr.append({"threshold": t_q, "fallback_rate": float(1.0 - keep.mean()),
                           "upsampled_psnr_min": float(psnr_c[keep].min()),
                           "upsampled_psnr_mean": float(psnr_c[keep].mean())})
-    vs_oracle = None
+    oracle_job = None
     if not args.no_cpu and args.oracle_frames > 0:
-        vs_oracle = learned_vs_oracle(args, r, scenes, scene_ids, P, K, W, H, thr, torch)
+        oracle_job = learned_oracle_job(args, r, scene_ids, P, K, W, H, thr, torch)
     net = network_roofline(r, scene_ids, P, K, W, H, n, torch)
+    held = held_out_scene_split(args, r, sids, W, H, torch) if args.held_out_split else None
     # where the step's time goes: the low-resolution render of every camera
     # (graph-replayed, as inside the form), the network, and the rest (the
     # fallback cameras' full-resolution render, scores, the head)
@@ -245,7 +246,9 @@ def learned_form(args, r, scenes, sids, scene_ids, P, K, W, H, n, out, ms_graph,
                 "reference": "GPU full-resolution render of the same cameras; frames that "
                              "fall back are that render itself and are not counted"},
             "fallback_vs_threshold_calibration": curve_thr,
-            "vs_oracle": vs_oracle,
+            "held_out_scene_split": held,
+            "vs_oracle": None,   # filled in by the CPU leg
+            "_oracle_job": oracle_job,
             "psnr_upsampled_only_db": {"heldout_mean_trained": float(psnr_c.mean()),
                                        "heldout_mean_bilinear": float(psnr_bilinear.mean())},
             "train": {"pairs": int(steps * args.train_batch), "batch": args.train_batch,
@@ -254,41 +257,126 @@ def learned_form(args, r, scenes, sids, scene_ids, P, K, W, H, n, out, ms_graph,
             "network": net}
 
 
-def learned_vs_oracle(args, r, scenes, scene_ids, P, K, W, H, thr, torch):
-    """The learned form judged by the FP64 oracle on a seeded subset of the
-    evaluation cameras: PSNR and max-abs RGB error of every frame (upsampled
-    or fallen back), and of the upsampled frames alone."""
-    import oracle
+def held_out_scene_split(args, r, sids, W, H, torch):
+    """Generalisation to scenes the network never saw: a second network is
+    trained like the first on pairs of 24 of the 32 scenes (every fourth
+    scene held out), then judged against the full-resolution render on
+    cameras of the 8 held-out scenes, beside bilinear upsampling and the
+    network trained on every scene. The first network's weights are put
+    back afterwards."""
     import scenegen
     k = args.workload
-    pick = scenegen.camera_subset(k, args.oracle_frames, seed=31)
-    ids = scene_ids[pick]
-    Pp, Kp = P[torch.as_tensor(pick).cuda()].contiguous(), K[torch.as_tensor(pick).cuda()].contiguous()
-    rgb, _, score, nf = r.render_upsampled(ids, Pp, Kp, W, H, threshold=thr)
-    rgb, score = rgb.cpu().numpy(), score.cpu().numpy()
-    cams = scenegen.make_cameras(k)
-    threads = min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "64")))
+    held = [s for s in range(len(sids)) if s % 4 == 3]
+    main_w = r.up_get()
+    ev = scenegen.sampled_cameras(k, args.calib_cams * 4, seed=4)
+    sel = np.nonzero(np.isin(ev["scene_ids"], held))[0][:args.calib_cams // 2]
+    ids = np.array([sids[i] for i in ev["scene_ids"][sel]], np.int32)
+    Pe = torch.as_tensor(ev["poses"][sel]).cuda()
+    Ke = torch.as_tensor(ev["intrinsics"][sel]).cuda()
+    full = r.render(ids, Pe, Ke, W, H, alpha=False)
+
+    def psnr_now():
+        up = r.render_upsampled(ids, Pe, Ke, W, H)
+        return r.frame_psnr(up[0], full[0]).cpu().numpy()
+
+    p_all = psnr_now()
+    r.up_init(0)
+    p_bil = psnr_now()
+    tr = scenegen.sampled_cameras(k, args.train_pairs * 2, seed=5)
+    keep = np.nonzero(~np.isin(tr["scene_ids"], held))[0][:args.train_pairs]
+    tr_ids = np.array([sids[i] for i in tr["scene_ids"][keep]], np.int32)
+    steps = max(1, len(keep) // args.train_batch)
     t = time.time()
-    psnr, err = [], []
+    r.up_train(tr_ids, tr["poses"][keep], tr["intrinsics"][keep], W, H, batch=args.train_batch,
+               steps=steps, lr=2e-3, lr_min=1e-4)
+    t_train = time.time() - t
+    p_held = psnr_now()
+    r.up_set(main_w)
+    log(f"held-out scenes ({len(held)} scenes, {len(sel)} cameras): network trained without "
+        f"them {p_held.mean():.2f} dB, trained on every scene {p_all.mean():.2f} dB, bilinear "
+        f"{p_bil.mean():.2f} dB ({steps} steps in {t_train:.1f}s)")
+    return {"held_out_scenes": held, "cameras": int(len(sel)), "train_steps": steps,
+            "psnr_db_mean_trained_without_them": float(p_held.mean()),
+            "psnr_db_p5_trained_without_them": float(np.percentile(p_held, 5)),
+            "psnr_db_mean_trained_on_all": float(p_all.mean()),
+            "psnr_db_mean_bilinear": float(p_bil.mean()),
+            "reference": "GPU full-resolution render of the same cameras"}
+
+
+def learned_oracle_job(args, r, scene_ids, P, K, W, H, thr, torch):
+    """GPU side of the learned form's oracle check, on a seeded subset of the
+    evaluation cameras: the upsampled render with the calibrated fallback and
+    with none (the network alone), plus the low-resolution inputs and the
+    weights, so that the CPU leg can run the oracle's network on them."""
+    import scenegen
+    pick = scenegen.camera_subset(args.workload, args.oracle_frames, seed=31)
+    ids = scene_ids[pick]
+    idx = torch.as_tensor(pick).cuda()
+    Pp, Kp = P[idx].contiguous(), K[idx].contiguous()
+    rgb, _, score, nf = r.render_upsampled(ids, Pp, Kp, W, H, threshold=thr)
+    rgb_net = r.render_upsampled(ids, Pp, Kp, W, H)[0]
+    m = min(args.oracle_net_frames, len(pick))
+    lo_rgb, lo_depth, _ = r.render(ids[:m], Pp[:m], (Kp[:m] / 4).contiguous(), W // 4, H // 4,
+                                   alpha=False)
+    return {"pick": pick, "thr": thr, "nf": nf, "rgb": rgb.cpu().numpy(),
+            "rgb_net": rgb_net.cpu().numpy(), "score": score.cpu().numpy(),
+            "lo_rgb": lo_rgb.cpu().numpy(), "lo_depth": lo_depth.cpu().numpy(),
+            "params": r.up_get()}
+
+
+def learned_vs_oracle(job, k, scenes, W, H, threads):
+    """CPU leg of the learned form's oracle check: PSNR and max-abs RGB error
+    against the FP64 oracle render of every picked frame (the form with its
+    fallback, its upsampled frames alone, and the network alone on every
+    frame), and the oracle's own network on the first frames' low-resolution
+    inputs, timed (frames/s) and compared with the GPU network's output."""
+    import oracle
+    import scenegen
+    from oracle import upsampler as U
+    pick, thr = job["pick"], job["thr"]
+    cams = scenegen.make_cameras(k)
+    t = time.time()
+    psnr, err, psnr_n, err_n = [], [], [], []
     for i, c in enumerate(pick):
         sc = scenes[int(cams["scene_ids"][c])]
-        ref = oracle.render(sc, cams["poses"][c], cams["intrinsics"][c], W, H, threads=threads).rgb
-        a, b = np.clip(rgb[i].astype(np.float64), 0, 1), np.clip(ref, 0, 1)
-        mse = float(((a - b) ** 2).mean())
-        psnr.append(10.0 * np.log10(1.0 / max(mse, 1e-12)))
-        err.append(float(np.abs(a - b).max()))
-    psnr, err = np.array(psnr), np.array(err)
-    up = ~(score > thr)
-    log(f"learned vs oracle ({len(pick)} frames, {time.time() - t:.1f}s): PSNR mean "
-        f"{psnr.mean():.2f} dB, upsampled frames {psnr[up].mean() if up.any() else float('nan'):.2f}"
-        f" dB ({int(up.sum())}), max-abs RGB {err.max():.3f}")
-    return {"frames": int(len(pick)), "fallback_frames": int(nf),
+        ref = np.clip(oracle.render(sc, cams["poses"][c], cams["intrinsics"][c], W, H,
+                                    threads=threads).rgb, 0, 1)
+        for out, ps, er in ((job["rgb"], psnr, err), (job["rgb_net"], psnr_n, err_n)):
+            a = np.clip(out[i].astype(np.float64), 0, 1)
+            mse = float(((a - ref) ** 2).mean())
+            ps.append(10.0 * np.log10(1.0 / max(mse, 1e-12)))
+            er.append(float(np.abs(a - ref).max()))
+    psnr, err, psnr_n, err_n = map(np.array, (psnr, err, psnr_n, err_n))
+    up = ~(job["score"] > thr)
+    log(f"learned vs oracle ({len(pick)} frames, {time.time() - t:.1f}s): form PSNR mean "
+        f"{psnr.mean():.2f} dB, its upsampled frames "
+        f"{psnr[up].mean() if up.any() else float('nan'):.2f} dB ({int(up.sum())}); network "
+        f"alone {psnr_n.mean():.2f} dB (p5 {np.percentile(psnr_n, 5):.2f}), max-abs RGB "
+        f"{err_n.max():.3f}")
+    # the oracle's network (FP64) on the same low-resolution inputs
+    x0 = U.make_input(job["lo_rgb"].astype(np.float64), job["lo_depth"].astype(np.float64))
+    params = U.unflatten(job["params"].astype(np.float64))
+    t0 = time.perf_counter()
+    pred, _ = U.forward(x0, params)
+    dt = time.perf_counter() - t0
+    m = len(x0)
+    gpu = job["rgb_net"][:m].astype(np.float64)
+    rel_l2 = float(np.linalg.norm(gpu - pred[..., :3]) / np.linalg.norm(pred[..., :3]))
+    log(f"oracle network: {m} frames in {dt:.1f}s ({m / dt:.2f} frames/s); GPU network "
+        f"relative L2 {rel_l2:.2e}")
+    return {"frames": int(len(pick)), "fallback_frames": int(job["nf"]),
             "psnr_db_mean": float(psnr.mean()), "psnr_db_p5": float(np.percentile(psnr, 5)),
             "max_abs_rgb": float(err.max()),
             "upsampled_frames": int(up.sum()),
             "upsampled_psnr_db_mean": float(psnr[up].mean()) if up.any() else None,
             "upsampled_max_abs_rgb": float(err[up].max()) if up.any() else None,
-            "reference": "FP64 oracle render, RGB clamped to [0, 1]"}
+            "network_alone_psnr_db_mean": float(psnr_n.mean()),
+            "network_alone_psnr_db_p5": float(np.percentile(psnr_n, 5)),
+            "network_alone_max_abs_rgb": float(err_n.max()),
+            "reference": "FP64 oracle render, RGB clamped to [0, 1]",
+            "oracle_network": {"frames": m, "seconds": dt, "frames_per_s": m / dt,
+                               "threads": "numpy (BLAS threads)",
+                               "gpu_network_rel_l2": rel_l2}}
 
 
 # multiply-accumulates per low-resolution pixel of the 4x upsampler: 3x3
@@ -448,6 +536,10 @@ def main():
     ap.add_argument("--psnr-target", type=float, default=35.0)
     ap.add_argument("--oracle-frames", type=int, default=128,
                     help="evaluation frames of the learned form checked against the FP64 oracle")
+    ap.add_argument("--no-held-out-split", dest="held_out_split", action="store_false",
+                    help="skip training a second upsampler without 8 of the scenes")
+    ap.add_argument("--oracle-net-frames", type=int, default=32,
+                    help="of those, frames the oracle's FP64 network runs on (timed)")
     ap.add_argument("--stress-steps", type=int, default=10,
                     help="consecutive sim steps of the stress workload timed beside the default "
                          "workload (0: skip that leg)")
@@ -627,11 +719,18 @@ def main():
     if not args.only_batched and not args.no_backward and args.workload == 2:
         forms["backward"] = backward_leg(args, r, torch)
 
+    # the CPU leg: the oracle timed on a sample of the workload (the
+    # baseline) and the learned form's frames judged by the oracle
     cpu = None
+    job = forms.get("learned", {}).pop("_oracle_job", None)
     if not args.no_cpu:
         threads = min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "64")))
         cpu = cpu_baseline(args.workload, scenes, cams, W, H, args.cpu_seconds, threads)
         log(f"cpu oracle: {cpu['value']:.3f} frames/s on {threads} threads")
+        if job is not None:
+            forms["learned"]["vs_oracle"] = learned_vs_oracle(job, args.workload, scenes, W, H,
+                                                              threads)
+    del job
 
     # algorithmic HBM bytes of one step: outputs (RGB + depth [+ alpha], FP32),
     # every scene's parameters read once, 24 B per tile instance
