@@ -34,7 +34,11 @@
  * Errors: every call returns GS_OK (0) or a negative GS_ERR_* code and never
  * throws; gs_last_error() describes the last failure of that context.
  * Argument validation is synchronous. A context is not thread-safe: use one
- * per thread or lock around it.
+ * per thread or lock around it. Its calls share the context's work buffers:
+ * a render (any gs_render_* call) enqueued on another stream than the
+ * previous render starts on the device only after that render; the
+ * upsampler calls are ordered only by their stream, so enqueue them on the
+ * renders' stream or order the streams with events.
  */
 #ifndef GS_H
 #define GS_H

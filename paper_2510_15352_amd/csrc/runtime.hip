@@ -791,6 +791,9 @@ int render_impl(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
         (batched && !o.timing) ? (o.streams > 0 ? std::min<int>(o.streams, kLanes) : kLanes) : 1;
     sync_scene_table(ctx);
     poll_status(ctx);
+    // renders share the context's work buffers: one enqueued on another
+    // stream than the last one starts after it on the device
+    if (ctx->pending) HIP_CHECK(hipStreamWaitEvent(st, ctx->ev_done, 0));
     char mask_key[32];
     snprintf(mask_key, sizeof mask_key, "|m%p", (const void *)cam_mask);
     const std::string tail = "|l" + std::to_string(n_lanes) + "|b" +
@@ -914,6 +917,7 @@ int render_backward_impl(gs_ctx *ctx, int32_t scene_id, int32_t n_cams, const fl
     ch.chunk = o.chunk_cams > 0 ? std::min(o.chunk_cams, kMaxChunkCams) : 512;
     ch.persistent = 0;
     sync_scene_table(ctx);
+    if (ctx->pending) HIP_CHECK(hipStreamWaitEvent(st, ctx->ev_done, 0));
     ctx->last = gs_stats{};
     int regrows = 0;
     for (int attempt = 0; attempt < 6; ++attempt) {

@@ -318,6 +318,25 @@ def test_async_renders_back_to_back_equal_waiting_renders(gpu_renderer, w1):
             for x, y in zip(ref, got):
                 assert np.array_equal(x, y.cpu().numpy())
     gpu_renderer.drop_graphs()
+    # the second render on another stream: it shares the context's work
+    # buffers, so it must start only after the first (nothing else orders
+    # them: the other stream waits only for the inputs, made before both)
+    s2 = torch.cuda.Stream()
+    for use_graph in (False, True):
+        P, P2 = torch.as_tensor(Pa).cuda(), torch.as_tensor(Pb).cuda()
+        outs = [gpu_renderer.alloc_outputs(8, 640, 480) for _ in range(2)]
+        gpu_renderer.render(ids, P, K, 640, 480, out=outs[1], use_graph=use_graph)  # sizes
+        torch.cuda.synchronize()
+        s2.wait_stream(torch.cuda.current_stream())
+        gpu_renderer.render(ids, P, K, 640, 480, out=outs[0], use_graph=use_graph)
+        with torch.cuda.stream(s2):
+            gpu_renderer.render(ids, P2, K, 640, 480, out=outs[1], use_graph=use_graph)
+        torch.cuda.synchronize()
+        gpu_renderer.status(wait=True)
+        for ref, got in zip(refs, outs):
+            for x, y in zip(ref, got):
+                assert np.array_equal(x, y.cpu().numpy()), use_graph
+    gpu_renderer.drop_graphs()
 
 
 def test_async_overflow_is_reported_and_next_render_complete(gpu_renderer, w1):
