@@ -57,12 +57,12 @@ def _run(gpu_renderer, k, step, n_sample, seed):
 
 
 def test_workload2_all_4096_cameras_sampled_parity(gpu_renderer):
-    st = _run(gpu_renderer, 2, 0, 12, seed=5)
+    st = _run(gpu_renderer, 2, 0, 64, seed=5)
     assert st["visible"] > 0 and st["regrows"] == 0
 
 
 def test_workload4_stress_step_sampled_parity(gpu_renderer):
-    _run(gpu_renderer, 4, 37, 8, seed=9)
+    _run(gpu_renderer, 4, 37, 24, seed=9)
 
 
 def test_autotuner_choice_is_used_and_bitwise_identical(gpu_renderer):
