@@ -421,8 +421,8 @@ def stress_leg(args, r, torch):
     over a few consecutive sim steps: every camera advances along its
     trajectory each step, the step's poses are copied into the buffer the
     captured graph reads and the graph is replayed (every stage recomputed).
-    Fixed choice (16x8 tiles, LDS batch 64: the autotuner's pick for this
-    workload), so the leg needs no tuning time. Also the pair counts of one
+    Fixed choice (16x8 tiles, LDS batch 64, 64-camera chunks: the
+    autotuner's pick for this workload), so the leg needs no tuning time. Also the pair counts of one
     step (instrumented raster)."""
     import scenegen
     k = 4
@@ -439,7 +439,7 @@ def stress_leg(args, r, torch):
     P = trajd[0].clone()
     K = torch.as_tensor(traj["intrinsics"]).cuda()
     out = r.alloc_outputs(n, W, H, alpha=False)
-    kw = dict(tile=(16, 8), lds_batch=64, persistent=0)
+    kw = dict(tile=(16, 8), lds_batch=64, persistent=0, chunk_cams=64)
 
     def step(i):
         P.copy_(trajd[i % args.stress_steps])

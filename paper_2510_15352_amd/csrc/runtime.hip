@@ -1892,7 +1892,7 @@ int gs_autotune(gs_ctx *ctx, int32_t n_cams, const int32_t *scene_ids, const flo
         cands.push_back(Choice{});
         const int shapes[][2] = {{16, 16}, {32, 8}, {16, 8}, {8, 8}, {32, 16}};
         const int batches[] = {128, 64, 256};
-        const int chunks[] = {512, 1024, 256};
+        const int chunks[] = {512, 1024, 256, 128, 64};
         for (auto &s : shapes)
             for (int b : batches)
                 if (raster_supported(s[0], s[1], b))
