@@ -584,13 +584,20 @@ __global__ __launch_bounds__(kBS) void k_seg_scatter(
         const uint32_t i = st.start + (uint32_t)(wave * 64 * kSegKPT + k * 64) + lane;
         const bool valid = i < st.end;
         dig[k] = (uint32_t)(key[k] >> shift) & mask;
-        uint64_t peers = __ballot(valid);
+        // lanes with the same digit: for every digit bit keep the lanes
+        // whose bit equals this lane's, i.e. AND with ~(ballot ^ t), t = 0
+        // or all ones as the bit is clear or set (one 3-input bit operation
+        // per 32-bit half)
+        const uint64_t vm = __ballot(valid);
+        uint32_t plo = (uint32_t)vm, phi = (uint32_t)(vm >> 32);
 #pragma unroll
         for (int bit = 0; bit < RB; ++bit) {
-            const bool on = (dig[k] >> bit) & 1u;
-            const uint64_t m = __ballot(on);
-            peers &= on ? m : ~m;
+            const uint32_t t = (uint32_t)((int32_t)(dig[k] << (31 - bit)) >> 31);
+            const uint64_t m = __ballot(t != 0u);
+            plo &= ~((uint32_t)m ^ t);
+            phi &= ~((uint32_t)(m >> 32) ^ t);
         }
+        const uint64_t peers = ((uint64_t)phi << 32) | plo;
         const uint32_t rank = (uint32_t)__popcll(peers & lt);
         const uint32_t before = valid ? cnt[dig[k]] : 0u;
         lrank[k] = before + rank;
