@@ -30,10 +30,25 @@ constexpr float kLn2 = 0.69314718055994530942f;
 // log2(e) / 2: the record's conic factor is the conic's scaled by its root
 constexpr float kKappa2 = 0.72134752044448170368f;
 
-__device__ __forceinline__ float wave_sum(float v)
+// Sum over the wave's 64 lanes with DPP moves (no LDS round trips): pairs,
+// quads, half rows and rows of 16 in every lane, then row 0 into row 1 and
+// row 2 into row 3, then rows 0-1 into rows 2-3; the total ends in lane 63.
+// The order of the additions is fixed, so the sum is deterministic.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp_add(float v)
 {
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) v += __shfl_down(v, d, 64);
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK,
+                                                           0xF, true));
+}
+
+__device__ __forceinline__ float wave_sum_to_lane63(float v)
+{
+    v = dpp_add<0xB1>(v);        // quad_perm [1, 0, 3, 2]
+    v = dpp_add<0x4E>(v);        // quad_perm [2, 3, 0, 1]
+    v = dpp_add<0x124>(v);       // row_ror 4
+    v = dpp_add<0x128>(v);       // row_ror 8
+    v = dpp_add<0x142, 0xA>(v);  // row_bcast 15 into rows 1 and 3
+    v = dpp_add<0x143, 0xC>(v);  // row_bcast 31 into rows 2 and 3
     return v;
 }
 
@@ -184,7 +199,8 @@ __global__ __launch_bounds__(256) void k_bwd_raster(BwdArgs a, uint32_t n_items)
                     if (acc) {
                         const float gi = fmaf(gr, R1.x, fmaf(gg, R1.y, fmaf(gb, R1.z, fmaf(gz, R1.w, gw))));
                         const float s = tot - pre - w * gi;
-                        const float da = T * gi - s / (1.0f - alpha);
+                        // approximate reciprocals (1 ulp): gradients, not decisions
+                        const float da = T * gi - s * __builtin_amdgcn_rcpf(1.0f - alpha);
                         pre = fmaf(w, gi, pre);
                         const bool clamped = raw > kAlphaMax;
                         const float dq = clamped ? 0.0f : -kLn2 * alpha * da;
@@ -195,15 +211,15 @@ __global__ __launch_bounds__(256) void k_bwd_raster(BwdArgs a, uint32_t n_items)
                         v[2] = dq * kKappa2 * dx * dx;
                         v[3] = dq * 2.0f * kKappa2 * dx * dy;
                         v[4] = dq * kKappa2 * dy * dy;
-                        v[5] = clamped ? 0.0f : da * (alpha / o);
+                        v[5] = clamped ? 0.0f : da * (alpha * __builtin_amdgcn_rcpf(o));
                         v[6] = gr * w;
                         v[7] = gg * w;
                         v[8] = gb * w;
                         v[9] = gz * w;
                     }
 #pragma unroll
-                    for (int t = 0; t < kBwdVals; ++t) v[t] = wave_sum(v[t]);
-                    if (lane == 0) {
+                    for (int t = 0; t < kBwdVals; ++t) v[t] = wave_sum_to_lane63(v[t]);
+                    if (lane == 63) {
                         float *dst = a.partial + ((size_t)LI[k].x * kBwdWaves + wave) * kBwdVals;
 #pragma unroll
                         for (int t = 0; t < kBwdVals; ++t) dst[t] = v[t];
