@@ -41,15 +41,43 @@ __device__ __forceinline__ float dpp_add(float v)
                                                            0xF, true));
 }
 
-__device__ __forceinline__ float wave_sum_to_lane63(float v)
+// Sum over one row of 16 lanes, in every lane of the row.
+__device__ __forceinline__ float row_sum(float v)
 {
-    v = dpp_add<0xB1>(v);        // quad_perm [1, 0, 3, 2]
-    v = dpp_add<0x4E>(v);        // quad_perm [2, 3, 0, 1]
-    v = dpp_add<0x124>(v);       // row_ror 4
-    v = dpp_add<0x128>(v);       // row_ror 8
-    v = dpp_add<0x142, 0xA>(v);  // row_bcast 15 into rows 1 and 3
-    v = dpp_add<0x143, 0xC>(v);  // row_bcast 31 into rows 2 and 3
+    v = dpp_add<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v = dpp_add<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v = dpp_add<0x124>(v);  // row_ror 4
+    v = dpp_add<0x128>(v);  // row_ror 8
     return v;
+}
+
+// (first, second) of a swap of the odd half-waves (rows of 32 lanes, W = 32)
+// or odd rows of 16 lanes (W = 16) of a with the even ones of b, added:
+// lanes of even rows get a's sum over the row pair, odd rows b's.
+template <int W>
+__device__ __forceinline__ float swap_add(float a, float b)
+{
+    const auto r = W == 32 ? __builtin_amdgcn_permlane32_swap(__float_as_uint(a),
+                                                              __float_as_uint(b), false, false)
+                           : __builtin_amdgcn_permlane16_swap(__float_as_uint(a),
+                                                              __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// The ten per-lane values summed over the wave and spread over its rows of
+// 16 lanes (every addition in a fixed order): values k and k + 5 are paired
+// across the two half-waves, then (0, 1), (2, 3) and (4, 4) across rows, and
+// each row is summed. Afterwards every lane of row r (r = lane / 16) holds
+// in q[0] the total of value (r & 1) + 5 (r >> 1), in q[1] that of value
+// 2 + (r & 1) + 5 (r >> 1), and in q[2] that of value 4 + 5 (r >> 1).
+__device__ __forceinline__ void wave_sum10(const float *v, float *q)
+{
+    float p[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) p[k] = swap_add<32>(v[k], v[k + 5]);
+    q[0] = row_sum(swap_add<16>(p[0], p[1]));
+    q[1] = row_sum(swap_add<16>(p[2], p[3]));
+    q[2] = row_sum(swap_add<16>(p[4], p[4]));
 }
 
 // ------------------------------------------------- emission positions --
@@ -217,12 +245,16 @@ __global__ __launch_bounds__(256) void k_bwd_raster(BwdArgs a, uint32_t n_items)
                         v[8] = gb * w;
                         v[9] = gz * w;
                     }
-#pragma unroll
-                    for (int t = 0; t < kBwdVals; ++t) v[t] = wave_sum_to_lane63(v[t]);
-                    if (lane == 63) {
+                    static_assert(kBwdVals == 10, "the wave sum spreads ten values");
+                    float q[3];
+                    wave_sum10(v, q);
+                    if ((lane & 15u) == 0u) {
+                        const int r = (int)(lane >> 4);
+                        const int t0 = (r & 1) + 5 * (r >> 1);
                         float *dst = a.partial + ((size_t)LI[k].x * kBwdWaves + wave) * kBwdVals;
-#pragma unroll
-                        for (int t = 0; t < kBwdVals; ++t) dst[t] = v[t];
+                        dst[t0] = q[0];
+                        dst[t0 + 2] = q[1];
+                        if ((r & 1) == 0) dst[4 + 5 * (r >> 1)] = q[2];
                     }
                 }
                 T = acc ? Tn : (hit ? -fabsf(T) : T);
