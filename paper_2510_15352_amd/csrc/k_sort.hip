@@ -28,14 +28,25 @@ constexpr int kBS = 256;          // block size of scan / sort kernels
 constexpr int kWaves = kBS / 64;  // waves per block
 constexpr uint32_t kMaxBlocks = 4096;  // blocks of a scan or sort pass
 
+// v plus the value of a lane chosen by a DPP pattern (0 where the pattern
+// has no source lane or the row is masked off).
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint32_t dpp_add_u32(uint32_t v)
+{
+    return v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, true);
+}
+
+// Inclusive scan over the wave with DPP moves (no LDS round trips): shifts
+// by 1, 2, 4 and 8 lanes inside each row of 16, then row 0's total into
+// row 1 and row 2's into row 3, then rows 0-1's total into rows 2 and 3.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
-    const uint32_t lane = __lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t t = __shfl_up(v, d, 64);
-        if (lane >= (uint32_t)d) v += t;
-    }
+    v = dpp_add_u32<0x111>(v);       // row_shr 1
+    v = dpp_add_u32<0x112>(v);       // row_shr 2
+    v = dpp_add_u32<0x114>(v);       // row_shr 4
+    v = dpp_add_u32<0x118>(v);       // row_shr 8
+    v = dpp_add_u32<0x142, 0xA>(v);  // row_bcast 15 into rows 1 and 3
+    v = dpp_add_u32<0x143, 0xC>(v);  // row_bcast 31 into rows 2 and 3
     return v;
 }
 
