@@ -511,6 +511,9 @@ __device__ __forceinline__ bool seg_tile(const uint32_t *seg, const uint32_t *tp
     return true;
 }
 
+// copies of each digit counter per wave in the histogram kernel
+constexpr int kHistCopies = 4;
+
 template <typename K, int RB>
 __global__ __launch_bounds__(kBS) void k_seg_hist(const K *__restrict__ keys,
                                                   const uint32_t *__restrict__ seg,
@@ -518,7 +521,12 @@ __global__ __launch_bounds__(kBS) void k_seg_hist(const K *__restrict__ keys,
                                                   int shift, uint32_t *__restrict__ hist)
 {
     constexpr int R = 1 << RB;
-    __shared__ uint32_t h[R];
+    // kHistCopies counters per digit and wave, lane l counting into copy
+    // l mod kHistCopies (rows padded to an odd stride): lanes with the same
+    // digit mostly hit different addresses and banks (one shared set of
+    // counters serialised the atomics: 8-11 bank conflicts per access)
+    constexpr int NC = kWaves * kHistCopies, STRIDE = R + 1;
+    __shared__ uint32_t h[NC * STRIDE];
     SegTile st;
     if (!seg_tile<R>(seg, tp, n_seg, st)) return;
     // every key of the thread is loaded before the first atomic, so a tile
@@ -529,14 +537,20 @@ __global__ __launch_bounds__(kBS) void k_seg_hist(const K *__restrict__ keys,
         const uint32_t i = st.start + (uint32_t)(k * kBS) + threadIdx.x;
         key[k] = i < st.end ? keys[i] : K(0);
     }
-    for (int d = threadIdx.x; d < R; d += kBS) h[d] = 0;
+    for (int d = threadIdx.x; d < NC * STRIDE; d += kBS) h[d] = 0;
     __syncthreads();
+    uint32_t *hc = h + ((threadIdx.x >> 6) * kHistCopies + (__lane_id() % kHistCopies)) * STRIDE;
 #pragma unroll
     for (int k = 0; k < kSegKPT; ++k)
         if (st.start + (uint32_t)(k * kBS) + threadIdx.x < st.end)
-            atomicAdd(&h[(uint32_t)(key[k] >> shift) & (uint32_t)(R - 1)], 1u);
+            atomicAdd(&hc[(uint32_t)(key[k] >> shift) & (uint32_t)(R - 1)], 1u);
     __syncthreads();
-    for (int d = threadIdx.x; d < R; d += kBS) hist[st.hbase + d * st.nt + st.t] = h[d];
+    for (int d = threadIdx.x; d < R; d += kBS) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) c += h[q * STRIDE + d];
+        hist[st.hbase + d * st.nt + st.t] = c;
+    }
 }
 
 // Wave-private ranking: wave w ranks keys [w*64*KPT, (w+1)*64*KPT) of the
