@@ -50,6 +50,24 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
     return v;
 }
 
+// Inclusive max-scan over the wave (same DPP pattern as wave_incl_scan).
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint32_t dpp_max_u32(uint32_t v)
+{
+    return max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, true));
+}
+
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v)
+{
+    v = dpp_max_u32<0x111>(v);
+    v = dpp_max_u32<0x112>(v);
+    v = dpp_max_u32<0x114>(v);
+    v = dpp_max_u32<0x118>(v);
+    v = dpp_max_u32<0x142, 0xA>(v);
+    v = dpp_max_u32<0x143, 0xC>(v);
+    return v;
+}
+
 // Exclusive scan across the block (NW waves); `total` gets the block sum.
 template <int NW>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t &total, uint32_t *s_wave)
@@ -329,6 +347,7 @@ __global__ __launch_bounds__(kBS) void k_emit_down(
     uint32_t *__restrict__ inst_start)
 {
     __shared__ uint32_t s_wave[kWaves];
+    __shared__ uint32_t s_idx[kWaves * 64];
     __shared__ int s_cam;
     uint32_t start, end;
     block_range(*n_dev, nb, start, end);
@@ -382,17 +401,30 @@ __global__ __launch_bounds__(kBS) void k_emit_down(
             ++cam;
             cam_first = cam < n_cams ? vis_start[cam] : ~0u;
         }
-        const uint32_t first = __shfl(ex, 0, 64);
-        const uint32_t wave_total = __shfl(ex, 63, 64) + __shfl(cnt, 63, 64) - first;
+        // every lane is active here: lane 0 and lane 63 are read directly
+        const uint32_t first = (uint32_t)__builtin_amdgcn_readlane((int)ex, 0);
+        const uint32_t wave_total = (uint32_t)__builtin_amdgcn_readlane((int)ex, 63) +
+                                    (uint32_t)__builtin_amdgcn_readlane((int)cnt, 63) - first;
         const uint32_t lex = ex - first;
         // all lanes stay active through the shuffles; only the stores are masked
+        uint32_t *sidx = s_idx + (threadIdx.x >> 6) * 64;
         for (uint32_t k0 = 0; k0 < wave_total; k0 += 64) {
             const uint32_t k = k0 + lane;
-            // record of output position k: largest lane r with lex[r] <= k
-            int r = 0;
-#pragma unroll
-            for (int step = 32; step >= 1; step >>= 1)
-                if (__shfl(lex, r + step, 64) <= k) r += step;
+            // record of output position k: the last lane with instances whose
+            // first output position is at most k. The window's record starts
+            // are marked at their positions, the lane covering k0 at 0, and an
+            // inclusive max-scan over the window carries each start forward.
+            const uint64_t le = __ballot(cnt > 0u && lex <= k0);
+            const uint32_t cover = 63u - (uint32_t)__builtin_clzll(le);
+            sidx[lane] = 0u;
+            __builtin_amdgcn_wave_barrier();
+            if (cnt > 0u && lex > k0 && lex - k0 < 64u) sidx[lex - k0] = lane;
+            __builtin_amdgcn_wave_barrier();
+            uint32_t rr = sidx[lane];
+            if (lane == 0u) rr = cover;
+            rr = wave_incl_max(rr);
+            __builtin_amdgcn_wave_barrier();
+            const int r = (int)rr;
             const uint32_t j = k - __shfl(lex, r, 64);
             const uint32_t bw = (uint32_t)__shfl(tb.bw, r, 64);
             const uint32_t key0 = __shfl(kbase, r, 64);
