@@ -248,13 +248,20 @@ void scan_u32(const uint32_t *in, const uint32_t *n_dev, uint32_t n_max, uint32_
 
 // ------------------------------------------------------- fused compaction --
 
+constexpr int kCompactMaxCams = 4096;  // cameras of a chunk (segments of the sorts)
+
 __global__ __launch_bounds__(kBS) void k_compact_down(
     const uint64_t *__restrict__ vis, uint32_t n_words, int nb,
-    const uint32_t *__restrict__ partial, const uint32_t *__restrict__ cam_slot, int n_cams,
+    const uint32_t *__restrict__ cam_slot_g, int n_cams, const uint32_t *__restrict__ partial,
     const uint32_t *__restrict__ zbits, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
     uint32_t *__restrict__ seg_start)
 {
     __shared__ uint32_t s_wave[kWaves];
+    // the cameras' first slots, staged once per block: the searches below
+    // then wait on LDS rather than on a chain of dependent global loads
+    __shared__ uint32_t cam_slot[kCompactMaxCams];
+    for (int c = (int)threadIdx.x; c < n_cams; c += kBS) cam_slot[c] = cam_slot_g[c];
+    __syncthreads();
     uint32_t start, end;
     block_range(n_words, nb, start, end);
     uint32_t base = partial[blockIdx.x];
@@ -328,12 +335,14 @@ void compact_visible(const uint64_t *vis, uint32_t n_words, const uint32_t *cam_
                      uint32_t *seg_start, const ScanTemp &tmp, hipStream_t st)
 {
     if (n_words == 0) return;
+    if (n_cams < 1 || n_cams > kCompactMaxCams)
+        throw std::invalid_argument("compaction: 1..4096 cameras per chunk");
     // one step of kBS words per block where the block limit allows: each
     // word expands into up to 64 records, so small blocks keep enough of
     // them in flight
     const int nb = scan_reduce(LoadPopc{vis}, nullptr, n_words, n_vis_out, tmp, st, kBS);
-    hipLaunchKernelGGL(k_compact_down, dim3(nb), dim3(kBS), 0, st, vis, n_words, nb, tmp.partial,
-                       cam_slot, n_cams, zbits, keys, vals, seg_start);
+    hipLaunchKernelGGL(k_compact_down, dim3(nb), dim3(kBS), 0, st, vis, n_words, nb, cam_slot,
+                       n_cams, tmp.partial, zbits, keys, vals, seg_start);
     hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, st, n_vis_out, seg_start + n_cams);
 }
 
