@@ -150,7 +150,8 @@ def test_workload1_plain_equals_batched_bitwise(gpu_renderer, w1):
 
 @pytest.mark.parametrize("tile,batch,persistent", [((16, 16), 64, 0), ((32, 8), 128, 1),
                                                    ((8, 8), 64, 0), ((16, 8), 128, 1),
-                                                   ((32, 16), 64, 0), ((16, 16), 256, 1)])
+                                                   ((32, 16), 64, 0), ((16, 16), 256, 1),
+                                                   ((32, 8), 64, 1)])
 def test_every_tile_choice_is_bitwise_identical(gpu_renderer, w1, tile, batch, persistent):
     sc, sid, cams = w1
     idx = np.arange(0, 64, 4)
@@ -588,6 +589,13 @@ def test_pair_and_visibility_counters_match_oracle(gpu_renderer, w0, w1):
         assert rc["instances16"] <= st["instances"] <= rc["instances16"] * 1.01 + 3
         assert st["pairs_evaluated"] >= st["pairs_contrib"]
         assert st["pairs_issued"] >= st["pairs_evaluated"]
+        # a pixel meets the same records in the same order whatever the
+        # batch size, so the contributing and evaluated pairs do not change
+        gpu_renderer.render([sid], cams["poses"][c:c + 1], cams["intrinsics"][c:c + 1], W, H,
+                            count_pairs=True, tile=(16, 16), lds_batch=64)
+        st64 = gpu_renderer.stats()
+        assert st64["pairs_contrib"] == st["pairs_contrib"]
+        assert st64["pairs_evaluated"] == st["pairs_evaluated"]
 
 
 def test_trace_and_debug_modes(gpu_renderer, w0, capfd, monkeypatch):
