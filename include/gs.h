@@ -145,7 +145,10 @@ int gs_abi_sizes(int32_t *scene_desc, int32_t *render_opts, int32_t *stats);
 /* Fill opts with the defaults listed in gs_render_opts. */
 void gs_default_opts(gs_render_opts *opts);
 
-/* Create a context on HIP device `hip_device`. *out receives the handle. */
+/* Create a context on HIP device `hip_device`. *out receives the handle.
+ * Environment variables read here: GS_TRACE (one line per render on
+ * stderr), GS_DEBUG (eager renders wait after every stage and name the
+ * stage of a device error). */
 int gs_create(int hip_device, gs_ctx **out);
 
 /* Free every scene, workspace and captured graph of the context. */
