@@ -62,12 +62,14 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ ike
 // One block per (camera, tile); each wave owns an 8x8 pixel block, one pixel
 // per lane, and walks the tile's list on its own (no block barrier). Per
 // batch of B records, 64 at a time with one record per lane, the wave keeps
-// only the records that can reach its 8x8 rectangle (may_touch), appends
-// them in list order to a wave-private LDS list together with the record's
-// block-relative offsets E0, F0, then walks that list front to back. A
-// skipped record has alpha < 1/255 at every pixel of the wave, so the
-// per-pixel result is the same as walking the full tile list. A wave stops
-// once all of its pixels are done.
+// only the records that can reach the bounding rectangle of its live pixels
+// (may_touch; pixels outside the image and finished pixels are not live),
+// appends them in list order to a wave-private LDS list together with the
+// record's block-relative offsets E0, F0, then walks that list front to
+// back. A skipped record has alpha < 1/255 at every live pixel of the wave
+// and leaves the finished ones unchanged, so the per-pixel result is the
+// same as walking the full tile list. A wave stops once all of its pixels
+// are done.
 template <int TW, int TH, int B, bool COUNT = false>
 __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &a, float4 *sR0,
                                             float4 *sR1, float2 *sEF,
@@ -86,8 +88,6 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
     const int pxi = wx0 + (int)(lane & 7u), pyi = wy0 + (int)(lane >> 3);
     const bool inside = pxi < a.W && pyi < a.H;
     const float lx = (float)(lane & 7u), ly = (float)(lane >> 3);
-    // the wave's pixel rectangle, clipped to the image (extent in pixels)
-    const float ww = (float)(min(wx0 + 7, a.W - 1) - wx0), wh = (float)(min(wy0 + 7, a.H - 1) - wy0);
     const float cx0 = (float)wx0 + 0.5f, cy0 = (float)wy0 + 0.5f;
     const uint2 rg = a.ranges[(uint32_t)cl * (uint32_t)a.tiles_per_cam + (uint32_t)tile];
     float4 *L0 = sR0 + wave * B;
@@ -109,8 +109,20 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
         pB = a.rec[(size_t)pslot * 3 + 1];
         pC = a.rec[(size_t)pslot * 3 + 2];
     }
-    bool live = __ballot(s.T > 0.0f) != 0ull;
-    for (uint32_t base = rg.x; live && base < rg.y; base += B) {
+    uint64_t lm = __ballot(s.T > 0.0f);
+    for (uint32_t base = rg.x; lm != 0ull && base < rg.y; base += B) {
+        // The batch is culled against the bounding rectangle of the wave's
+        // live pixels (lane = 8 row + column): rows from the first and last
+        // live lane, columns from the OR of the eight rows. A finished pixel
+        // is left unchanged by every record, so a record that reaches none
+        // of the live ones is dropped like one outside the block.
+        const int r0 = __builtin_ctzll(lm) >> 3, r1 = (63 - __builtin_clzll(lm)) >> 3;
+        uint32_t cm = (uint32_t)lm | (uint32_t)(lm >> 32);
+        cm |= cm >> 16;
+        cm |= cm >> 8;
+        const int c0 = __builtin_ctz(cm & 0xffu), c1 = 31 - __builtin_clz(cm & 0xffu);
+        const float ox = (float)c0, oy = (float)r0;
+        const float lw = (float)(c1 - c0), lh = (float)(r1 - r0);
         int n = 0;
 #pragma unroll
         for (int sb = 0; sb < B / 64; ++sb) {
@@ -130,7 +142,7 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
                 R0 = make_float4(A.z, A.w, Bv.x, -__builtin_amdgcn_logf(Bv.y));
                 R1 = make_float4(Bv.z, Bv.w, C.x, C.y);
                 const float Xw = cx0 - A.x, Yw = cy0 - A.y;
-                hit = may_touch(R0.x, R0.y, R0.z, Xw, Yw, ww, wh, C.z);
+                hit = may_touch(R0.x, R0.y, R0.z, Xw + ox, Yw + oy, lw, lh, C.z);
                 E0 = fmaf(R0.x, Xw, R0.y * Yw);
                 F0 = R0.z * Yw;
             }
@@ -180,7 +192,7 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
                 }
             }
         }
-        live = __ballot(s.T > 0.0f) != 0ull;
+        lm = __ballot(s.T > 0.0f);
         __builtin_amdgcn_wave_barrier();  // list read before the next batch rewrites it
     }
     if (COUNT) {

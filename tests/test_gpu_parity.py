@@ -589,13 +589,14 @@ def test_pair_and_visibility_counters_match_oracle(gpu_renderer, w0, w1):
         assert rc["instances16"] <= st["instances"] <= rc["instances16"] * 1.01 + 3
         assert st["pairs_evaluated"] >= st["pairs_contrib"]
         assert st["pairs_issued"] >= st["pairs_evaluated"]
-        # a pixel meets the same records in the same order whatever the
-        # batch size, so the contributing and evaluated pairs do not change
+        # a pixel meets the same contributing records in the same order
+        # whatever the batch size (the batches are culled against the live
+        # pixels, so the evaluated pairs may differ)
         gpu_renderer.render([sid], cams["poses"][c:c + 1], cams["intrinsics"][c:c + 1], W, H,
                             count_pairs=True, tile=(16, 16), lds_batch=64)
         st64 = gpu_renderer.stats()
         assert st64["pairs_contrib"] == st["pairs_contrib"]
-        assert st64["pairs_evaluated"] == st["pairs_evaluated"]
+        assert st64["pairs_issued"] >= st64["pairs_evaluated"] >= st64["pairs_contrib"]
 
 
 def test_trace_and_debug_modes(gpu_renderer, w0, capfd, monkeypatch):
