@@ -16,6 +16,11 @@ namespace gs {
 constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTMin = 1e-4f;
+// The walk's scaled form of the same rules (see composite): thresholds on
+// alpha / kAlphaMax and on kAlphaMax x the transmittance, and log2(kAlphaMax).
+constexpr float kScaledAlphaMin = kAlphaMin / kAlphaMax;
+constexpr float kScaledTMin = kTMin * kAlphaMax;
+constexpr float kLog2AlphaMax = -0.0144995696951150891f;
 constexpr float kLowPass = 0.3f;
 constexpr float kTanClamp = 1.3f;
 // sqrt(log2(e) / 2): folds the -1/2 of the Gaussian exponent and the change
@@ -297,45 +302,51 @@ __device__ __forceinline__ bool project_gaussian(const CamParams &cam, float4 po
     return true;
 }
 
-// Per-pixel state of the front-to-back walk. The sign of T carries the stop
-// flag: T > 0 while the pixel is live; a stop negates it, keeping |T| as the
-// final transmittance.
+// Per-pixel state of the front-to-back walk: U = kAlphaMax x the
+// transmittance T. The sign of U carries the stop flag: U > 0 while the
+// pixel is live; a stop negates it, keeping |U| / kAlphaMax as the final
+// transmittance.
 struct Pixel {
-    float T, r, g, b, zw;
+    float U, r, g, b, zw;
 };
 
-// LDS form of a record: R0 = (ex, ey, fy, -log2(opacity)), R1 = (r, g, b, z),
+// LDS form of a record: R0 = (ex, ey, fy, log2(0.99) - log2(opacity)),
+// R1 = (r, g, b, z),
 // and per wave (E0, F0) = (ex Xw + ey Yw, fy Yw) with (Xw, Yw) = the wave's
 // 8x8 block origin + 0.5 - (u, v). For the pixel at (lx, ly) in the block
 // (integers 0..7) the conic factor terms are e = ex lx + ey ly + E0 and
-// f = fy ly + F0, and opacity * exp2(-(e^2 + f^2)) =
-// exp2(-(e^2 + f^2 - log2(opacity))). The blocks form the same 8x8 grid for
-// every tile shape, so a pixel's arithmetic does not depend on the tiling.
+// f = fy ly + F0, and opacity * exp2(-(e^2 + f^2)) / 0.99 =
+// exp2(-(e^2 + f^2 + R0.w)). The blocks form the same 8x8 grid for every
+// tile shape, so a pixel's arithmetic does not depend on the tiling.
 //
 // One step of the walk for one (pixel, Gaussian) pair: alpha clamped to
 // 0.99; skipped below 1/255; the walk stops (without this Gaussian) when the
 // new transmittance would fall under 1e-4; otherwise weight alpha T is
-// accumulated into colour and depth. Branch-free: a pair that does not
-// accumulate adds a zero weight, which leaves every sum bitwise unchanged;
-// once stopped, T < 0 makes every later Tn negative, so nothing accumulates.
-// Returns whether the pair was accumulated.
+// accumulated into colour and depth. In the scaled form a = alpha / 0.99 =
+// min(1, exp2(-q)) (the clamp is the exponential's own output clamp), the
+// weight is alpha T = a U and the new U is U - 0.99 a U, with the thresholds
+// scaled alike: one instruction fewer per pair than clamping alpha itself.
+// Branch-free: a pair that does not accumulate adds a zero weight, which
+// leaves every sum bitwise unchanged; once stopped, U < 0 makes every later
+// Un negative, so nothing accumulates. Returns whether the pair was
+// accumulated.
 __device__ __forceinline__ bool composite(Pixel &s, float lx, float ly, float4 R0, float4 R1,
                                           float E0, float F0)
 {
     const float e = fmaf(R0.x, lx, fmaf(R0.y, ly, E0));
     const float f = fmaf(R0.z, ly, F0);
     const float q = fmaf(e, e, fmaf(f, f, R0.w));
-    const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(-q));
-    const bool hit = alpha >= kAlphaMin;
-    const float wt = alpha * s.T;
-    const float Tn = s.T - wt;
-    const bool acc = hit & (Tn >= kTMin);
+    const float a = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(-q), 0.0f, 1.0f);
+    const bool hit = a >= kScaledAlphaMin;
+    const float wt = a * s.U;
+    const float Un = fmaf(-kAlphaMax, wt, s.U);
+    const bool acc = hit & (Un >= kScaledTMin);
     const float w = acc ? wt : 0.0f;
     s.r = fmaf(w, R1.x, s.r);
     s.g = fmaf(w, R1.y, s.g);
     s.b = fmaf(w, R1.z, s.b);
     s.zw = fmaf(w, R1.w, s.zw);
-    s.T = acc ? Tn : (hit ? -fabsf(s.T) : s.T);
+    s.U = acc ? Un : (hit ? -fabsf(s.U) : s.U);
     return acc;
 }
 

@@ -122,6 +122,7 @@ __global__ void k_bwd_zero(float *__restrict__ partial, const uint32_t *__restri
 // where S_i = sum_{j > i} w_j g_j + T_final gR . bg is the total minus the
 // prefix so far. Through a = o 2^-q (unless clamped at 0.99) with
 // q = e^2 + f^2, e = ex dx + ey dy, f = fy dy (dx = pixel centre - u), the
+// decisions taken in the forward's scaled form (a / 0.99, 0.99 T), the
 // pair contributes to (u, v, conic xx, conic xy, conic yy, opacity, r, g, b,
 // z). The ten sums over the wave go to partial[(instance * 4 + wave) * 10].
 __global__ __launch_bounds__(256) void k_bwd_raster(BwdArgs a, uint32_t n_items)
@@ -163,9 +164,9 @@ __global__ __launch_bounds__(256) void k_bwd_raster(BwdArgs a, uint32_t n_items)
     }
     float tot = 0.0f, gz = 0.0f, gw = 0.0f;
     for (int pass = 0; pass < 2; ++pass) {
-        float T = inside ? 1.0f : -1.0f;
+        float U = inside ? kAlphaMax : -1.0f;  // 0.99 x the transmittance
         float r = 0.0f, g = 0.0f, b = 0.0f, zw = 0.0f, ws = 0.0f, pre = 0.0f;
-        bool live = __ballot(T > 0.0f) != 0ull;
+        bool live = __ballot(U > 0.0f) != 0ull;
         for (uint32_t base = rg.x; live && base < rg.y; base += B) {
             int n = 0;
 #pragma unroll
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(256) void k_bwd_raster(BwdArgs a, uint32_t n_items)
                     const float4 A = a.rec[(size_t)slot * 3];
                     const float4 Bv = a.rec[(size_t)slot * 3 + 1];
                     const float4 C = a.rec[(size_t)slot * 3 + 2];
-                    R0 = make_float4(A.z, A.w, Bv.x, -__builtin_amdgcn_logf(Bv.y));
+                    R0 = make_float4(A.z, A.w, Bv.x, kLog2AlphaMax - __builtin_amdgcn_logf(Bv.y));
                     R1 = make_float4(Bv.z, Bv.w, C.x, C.y);
                     const float Xw = cx0 - A.x, Yw = cy0 - A.y;
                     hit = may_touch(R0.x, R0.y, R0.z, Xw, Yw, ww, wh, C.z);
@@ -207,12 +208,12 @@ __global__ __launch_bounds__(256) void k_bwd_raster(BwdArgs a, uint32_t n_items)
                 const float e = fmaf(R0.x, lx, fmaf(R0.y, ly, X.x));
                 const float f = fmaf(R0.z, ly, X.y);
                 const float q = fmaf(e, e, fmaf(f, f, R0.w));
-                const float raw = __builtin_amdgcn_exp2f(-q);
-                const float alpha = fminf(kAlphaMax, raw);
-                const bool hit = alpha >= kAlphaMin;
-                const float wt = alpha * T;
-                const float Tn = T - wt;
-                const bool acc = hit & (Tn >= kTMin);
+                const float raw = __builtin_amdgcn_exp2f(-q);  // alpha / 0.99, unclamped
+                const float sa = fminf(raw, 1.0f);
+                const bool hit = sa >= kScaledAlphaMin;
+                const float wt = sa * U;
+                const float Un = fmaf(-kAlphaMax, wt, U);
+                const bool acc = hit & (Un >= kScaledTMin);
                 const float w = acc ? wt : 0.0f;
                 if (pass == 0) {
                     r = fmaf(w, R1.x, r);
@@ -228,9 +229,10 @@ __global__ __launch_bounds__(256) void k_bwd_raster(BwdArgs a, uint32_t n_items)
                         const float gi = fmaf(gr, R1.x, fmaf(gg, R1.y, fmaf(gb, R1.z, fmaf(gz, R1.w, gw))));
                         const float s = tot - pre - w * gi;
                         // approximate reciprocals (1 ulp): gradients, not decisions
+                        const float alpha = kAlphaMax * sa, T = U * (1.0f / kAlphaMax);
                         const float da = T * gi - s * __builtin_amdgcn_rcpf(1.0f - alpha);
                         pre = fmaf(w, gi, pre);
-                        const bool clamped = raw > kAlphaMax;
+                        const bool clamped = raw > 1.0f;
                         const float dq = clamped ? 0.0f : -kLn2 * alpha * da;
                         const float o = __uint_as_float(LI[k].y);
                         const float dx = lx + X.z, dy = ly + X.w;
@@ -257,14 +259,14 @@ __global__ __launch_bounds__(256) void k_bwd_raster(BwdArgs a, uint32_t n_items)
                         if ((r & 1) == 0) dst[4 + 5 * (r >> 1)] = q[2];
                     }
                 }
-                T = acc ? Tn : (hit ? -fabsf(T) : T);
-                if (__ballot(T > 0.0f) == 0ull) break;
+                U = acc ? Un : (hit ? -fabsf(U) : U);
+                if (__ballot(U > 0.0f) == 0ull) break;
             }
-            live = __ballot(T > 0.0f) != 0ull;
+            live = __ballot(U > 0.0f) != 0ull;
             __builtin_amdgcn_wave_barrier();  // list read before the next batch rewrites it
         }
         if (pass == 0) {
-            const float tf = fabsf(T);
+            const float tf = fabsf(U) / kAlphaMax;
             gz = ws > 0.0f ? gd / ws : 0.0f;
             gw = ws > 0.0f ? ga - gd * zw / (ws * ws) : ga;
             tot = gr * r + gg * g + gb * b + gz * zw + gw * ws +

@@ -95,7 +95,7 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
     float2 *LE = sEF + wave * B;
     const uint64_t lt = lanemask_lt();
     Pixel s;
-    s.T = inside ? 1.0f : -1.0f;
+    s.U = inside ? kAlphaMax : -1.0f;
     s.r = 0.0f; s.g = 0.0f; s.b = 0.0f; s.zw = 0.0f;
     uint32_t n_eval = 0, n_contrib = 0, n_issue = 0;
     // Record of the lane in the current set of 64, in registers. The next
@@ -109,7 +109,7 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
         pB = a.rec[(size_t)pslot * 3 + 1];
         pC = a.rec[(size_t)pslot * 3 + 2];
     }
-    uint64_t lm = __ballot(s.T > 0.0f);
+    uint64_t lm = __ballot(s.U > 0.0f);
     for (uint32_t base = rg.x; lm != 0ull && base < rg.y; base += B) {
         // The batch is culled against the bounding rectangle of the wave's
         // live pixels (lane = 8 row + column): rows from the first and last
@@ -133,13 +133,13 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
             const uint32_t nj = j0 + 64u;
             pf = nj + lane < rg.y;
             if (pf) pslot = a.ivals[nj + lane];
-            // R0 = (ex, ey, fy, -log2 o), R1 = (r, g, b, z); centre (u, v),
+            // R0 = (ex, ey, fy, log2 0.99 - log2 o), R1 = (r, g, b, z); centre (u, v),
             // reach tau
             bool hit = false;
             float4 R0 = A, R1 = A;
             float E0 = 0.0f, F0 = 0.0f;
             if (have) {
-                R0 = make_float4(A.z, A.w, Bv.x, -__builtin_amdgcn_logf(Bv.y));
+                R0 = make_float4(A.z, A.w, Bv.x, kLog2AlphaMax - __builtin_amdgcn_logf(Bv.y));
                 R1 = make_float4(Bv.z, Bv.w, C.x, C.y);
                 const float Xw = cx0 - A.x, Yw = cy0 - A.y;
                 hit = may_touch(R0.x, R0.y, R0.z, Xw + ox, Yw + oy, lw, lh, C.z);
@@ -170,21 +170,21 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
                 const float4 R0 = L0[k + u], R1 = L1[k + u];
                 const float2 ef = LE[k + u];
                 if (COUNT) {
-                    n_eval += s.T > 0.0f;
+                    n_eval += s.U > 0.0f;
                     ++n_issue;
                     n_contrib += composite(s, lx, ly, R0, R1, ef.x, ef.y);
                 } else {
                     composite(s, lx, ly, R0, R1, ef.x, ef.y);
                 }
             }
-            if (__ballot(s.T > 0.0f) == 0ull) break;
+            if (__ballot(s.U > 0.0f) == 0ull) break;
         }
-        if (__ballot(s.T > 0.0f) != 0ull) {
+        if (__ballot(s.U > 0.0f) != 0ull) {
             for (; k < n; ++k) {
                 const float4 R0 = L0[k], R1 = L1[k];
                 const float2 ef = LE[k];
                 if (COUNT) {
-                    n_eval += s.T > 0.0f;
+                    n_eval += s.U > 0.0f;
                     ++n_issue;
                     n_contrib += composite(s, lx, ly, R0, R1, ef.x, ef.y);
                 } else {
@@ -192,7 +192,7 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
                 }
             }
         }
-        lm = __ballot(s.T > 0.0f);
+        lm = __ballot(s.U > 0.0f);
         __builtin_amdgcn_wave_barrier();  // list read before the next batch rewrites it
     }
     if (COUNT) {
@@ -212,7 +212,7 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
     if (inside) {
         const int64_t cg = a.cam_global[cl];
         const int64_t pix = (cg * a.H + pyi) * (int64_t)a.W + pxi;
-        const float T = fabsf(s.T);
+        const float T = fabsf(s.U) / kAlphaMax;
         const float accw = 1.0f - T;
         const float r = fmaf(T, a.bg_r, s.r), g = fmaf(T, a.bg_g, s.g), b = fmaf(T, a.bg_b, s.b);
         if (a.blend == 0) {
