@@ -41,9 +41,9 @@ HBM_PEAK = 8.0e12                      # B/s
 SLOTS_PER_PAIR = 20
 OPS_PER_VISIBLE = 300
 # VALU issue slots of every lane-pair the built raster walk issues (its ISA:
-# 17 full-rate instructions plus v_exp_f32 at quarter rate); this measures
+# 16 full-rate instructions plus v_exp_f32 at quarter rate); this measures
 # how busy the VALUs are, waste included, not algorithmic work.
-ISSUED_SLOTS = 21
+ISSUED_SLOTS = 20
 
 
 def log(msg):
@@ -679,7 +679,7 @@ def main():
                     "eval_over_contrib": evals / max(pairs, 1),
                     "issued_lanes_per_step": issued, "issued_over_contrib": issued / max(pairs, 1),
                     # the same roofline over every lane-pair the walk issues
-                    # (18 VALU instructions, v_exp_f32 at quarter rate: 21
+                    # (17 VALU instructions, v_exp_f32 at quarter rate: 20
                     # slots): how busy the VALUs are, waste included
                     "issued_frac": (issued / max(stage_n["raster"] / eager_steps, 1)) * ISSUED_SLOTS
                                    / (raster_launch_ms * 1e-3) / VALU_PEAK,
