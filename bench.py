@@ -107,6 +107,18 @@ def gen_workload(k):
     return w, scenes, cams
 
 
+def host_cpu_model():
+    """The host CPU's model name (first entry of /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def time_steps(fn, steps, torch):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -726,7 +738,10 @@ def main():
     if not args.no_cpu:
         threads = min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "64")))
         cpu = cpu_baseline(args.workload, scenes, cams, W, H, args.cpu_seconds, threads)
-        log(f"cpu oracle: {cpu['value']:.3f} frames/s on {threads} threads")
+        cpu["host_cpus"] = os.cpu_count()
+        cpu["cpu_model"] = host_cpu_model()
+        log(f"cpu oracle: {cpu['value']:.3f} frames/s on {threads} threads "
+            f"({cpu['cpu_model']}, {cpu['host_cpus']} CPUs on the host)")
         if job is not None:
             forms["learned"]["vs_oracle"] = learned_vs_oracle(job, args.workload, scenes, W, H,
                                                               threads)
