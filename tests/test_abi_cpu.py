@@ -55,3 +55,21 @@ def test_struct_layouts_match_library():
     assert [s.value for s in sizes] == [ctypes.sizeof(gs.binding.SceneDesc),
                                         ctypes.sizeof(gs.binding.RenderOpts),
                                         ctypes.sizeof(gs.binding.Stats)]
+
+
+def test_scaled_walk_constants():
+    """The raster walk runs on alpha / 0.99 and 0.99 x the transmittance:
+    its log2(0.99) literal and its scaled thresholds must come from the
+    fixed rules (alpha clamp 0.99, skip below 1/255, stop under 1e-4)."""
+    import numpy as np
+    src = open(os.path.join(ROOT, "paper_2510_15352_amd", "csrc", "gs_device.h")).read()
+
+    def const(name):
+        return re.search(r"constexpr float %s = ([^;]+);" % name, src).group(1).strip()
+
+    assert np.float32(const("kAlphaMax").rstrip("f")) == np.float32(0.99)
+    assert const("kAlphaMin") == "1.0f / 255.0f"
+    assert np.float32(const("kTMin").rstrip("f")) == np.float32(1e-4)
+    assert const("kScaledAlphaMin") == "kAlphaMin / kAlphaMax"
+    assert const("kScaledTMin") == "kTMin * kAlphaMax"
+    assert np.float32(const("kLog2AlphaMax").rstrip("f")) == np.float32(np.log2(0.99))
