@@ -78,6 +78,9 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
     static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are made of 8x8 wave blocks");
     static_assert(B % 64 == 0, "batches are whole sets of 64 records");
     constexpr int SX = TW / 8;
+    // tiles of at most two wave blocks (small splats, long lists) also test
+    // each record's pixel box against the live lanes
+    constexpr bool kBoxCull = TW * TH <= 128;
     // a masked-out camera keeps its frame (block-uniform test, before any work)
     if (a.cam_mask && a.cam_mask[a.cam_global[cl]] == 0u) return;
     // wave-uniform: kept in scalar registers with everything derived from it
@@ -143,6 +146,28 @@ __device__ __forceinline__ void raster_tile(int cl, int tile, const RasterArgs &
                 R1 = make_float4(Bv.z, Bv.w, C.x, C.y);
                 const float Xw = cx0 - A.x, Yw = cy0 - A.y;
                 hit = may_touch(R0.x, R0.y, R0.z, Xw + ox, Yw + oy, lw, lh, C.z);
+                if (kBoxCull && hit) {
+                    // The box of the ellipse q <= tau (half-widths
+                    // sqrt(tau) sqrt(ey^2 + fy^2) / (ex fy) and sqrt(tau) / fy,
+                    // widened for rounding) as a lane mask, against the
+                    // live lanes themselves rather than their rectangle.
+                    const float rt = fmaf(__builtin_sqrtf(C.z), 1.0001f, 1e-3f);
+                    const float ify = __builtin_amdgcn_rcpf(R0.z);
+                    const float hy = rt * ify;
+                    const float hx = rt * ify * __builtin_sqrtf(fmaf(R0.y, R0.y, R0.z * R0.z)) *
+                                     __builtin_amdgcn_rcpf(R0.x);
+                    const int c0 = (int)ceilf(fmaxf(-Xw - hx, 0.0f));
+                    const int c1 = (int)floorf(fminf(hx - Xw, 7.0f));
+                    const int r0 = (int)ceilf(fmaxf(-Yw - hy, 0.0f));
+                    const int r1 = (int)floorf(fminf(hy - Yw, 7.0f));
+                    if (c0 > c1 || r0 > r1) {
+                        hit = false;
+                    } else {
+                        const uint32_t cb = (2u << c1) - (1u << c0);
+                        const uint64_t rb = (~0ull >> (8 * (7 - r1))) & (~0ull << (8 * r0));
+                        hit = ((uint64_t)cb * 0x0101010101010101ull & rb & lm) != 0ull;
+                    }
+                }
                 E0 = fmaf(R0.x, Xw, R0.y * Yw);
                 F0 = R0.z * Yw;
             }
