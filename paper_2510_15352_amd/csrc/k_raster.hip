@@ -1,6 +1,6 @@
-// Tile ranges and the front-to-back rasteriser (every wave walks its own
-// culled copy of the tile's list), as a one-block-per-tile grid or a
-// persistent work queue; motion-blur pose and finishing kernels.
+// The front-to-back rasteriser (every wave walks its own culled copy of the
+// tile's list), as a one-block-per-tile grid or a persistent work queue;
+// motion-blur pose and finishing kernels.
 #include <algorithm>
 
 #include "gs_device.h"
@@ -25,37 +25,6 @@ __global__ void k_zero_u32(uint32_t *p, uint64_t n)
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = 0u;
-}
-
-// -------------------------------------------------------------- ranges --
-__global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ ikeys,
-                                                const uint32_t *__restrict__ n_dev,
-                                                uint2 *__restrict__ ranges)
-{
-    // four keys per thread (one 16-byte load) plus the neighbour on each
-    // side; ~0u stands for "no key" (keys are tile indices far below it)
-    const uint32_t n = *n_dev;
-    const uint32_t n4 = (n + 3u) >> 2;
-    const uint4 *k4 = reinterpret_cast<const uint4 *>(ikeys);
-    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < n4; g += gridDim.x * blockDim.x) {
-        const uint32_t i0 = g << 2;
-        uint32_t k[6];
-        k[0] = i0 == 0 ? ~0u : ikeys[i0 - 1];
-        if (i0 + 4u <= n) {
-            const uint4 v = k4[g];
-            k[1] = v.x; k[2] = v.y; k[3] = v.z; k[4] = v.w;
-        } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) k[1 + j] = i0 + (uint32_t)j < n ? ikeys[i0 + j] : ~0u;
-        }
-        k[5] = i0 + 4u < n ? ikeys[i0 + 4u] : ~0u;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (i0 + (uint32_t)j >= n) break;
-            if (k[j] != k[j + 1]) ranges[k[j + 1]].x = i0 + (uint32_t)j;
-            if (k[j + 2] != k[j + 1]) ranges[k[j + 1]].y = i0 + (uint32_t)j + 1u;
-        }
-    }
 }
 
 // -------------------------------------------------------------- raster --
@@ -376,14 +345,6 @@ void launch_zero_u32(uint32_t *p, uint64_t n, hipStream_t st)
     uint64_t blocks = (n + 255) / 256;
     if (blocks > 16384) blocks = 16384;
     hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
-}
-
-void launch_ranges(const uint32_t *ikeys, const uint32_t *n_dev, uint2 *ranges, uint32_t n_max,
-                   hipStream_t st)
-{
-    uint32_t blocks = (n_max / 4 + 255) / 256;
-    blocks = blocks < 1 ? 1 : (blocks > 16384 ? 16384 : blocks);
-    hipLaunchKernelGGL(k_ranges, dim3(blocks), dim3(256), 0, st, ikeys, n_dev, ranges);
 }
 
 #define GS_RASTER_CASES(X) \

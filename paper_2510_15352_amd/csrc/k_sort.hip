@@ -605,7 +605,7 @@ __global__ __launch_bounds__(kBS) void k_seg_scatter(
     uint32_t *__restrict__ vout, const uint32_t *__restrict__ seg,
     const uint32_t *__restrict__ tp, int n_seg, int shift, const uint32_t *__restrict__ hist,
     uint32_t seg_key_stride, const uint2 *__restrict__ pay_src, uint2 *__restrict__ pay_dst,
-    uint32_t pay_stride)
+    uint32_t pay_stride, uint2 *__restrict__ ranges)
 {
     constexpr int R = 1 << RB;
     constexpr int DPT = R >= kBS ? R / kBS : 1;  // digits owned by each thread
@@ -721,14 +721,43 @@ __global__ __launch_bounds__(kBS) void k_seg_scatter(
         else
             kout[g] = kk + add;
         vout[g] = v;
+        if (ranges) {
+            // Last pass: inside the run of digit d the keys are sorted (the
+            // earlier passes ordered the tile by the lower digits), and the
+            // run lands at consecutive positions. The first and last element
+            // of each key in the run bound that key's range; a key whose run
+            // continues in another tile's run is completed there, so the
+            // bounds are folded in with min / max.
+            const uint32_t run0 = s_toff[d];
+            const uint32_t run1 = d + 1u < (uint32_t)R ? s_toff[d + 1] : n_tile;
+            if (p == run0 || s_keys[p - 1] != kk) atomicMin(&ranges[kk + add].x, g);
+            if (p + 1u == run1 || s_keys[p + 1] != kk) atomicMax(&ranges[kk + add].y, g + 1u);
+        }
     }
+}
+
+// Tile ranges before the tile sort folds its bounds in: start ~0, end 0 (an
+// empty range for every tile no instance reaches).
+__global__ void k_fill_ranges(uint2 *__restrict__ ranges, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        ranges[i] = make_uint2(~0u, 0u);
+}
+
+void fill_ranges(uint2 *ranges, uint64_t n, hipStream_t st)
+{
+    if (n == 0) return;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_fill_ranges, dim3((unsigned)blocks), dim3(256), 0, st, ranges, n);
 }
 
 template <typename K, int RB>
 static int seg_sort_rb(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t *seg, int n_seg,
                        uint32_t n_max, int bits, uint32_t stride, const uint2 *pay_src,
                        uint2 *pay_dst, uint32_t pay_stride, const SegSortTemp &tmp,
-                       hipStream_t st)
+                       hipStream_t st, uint2 *ranges)
 {
     constexpr int R = 1 << RB;
     const uint32_t max_tiles =
@@ -747,7 +776,8 @@ static int seg_sort_rb(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t 
         const bool last = shift + RB >= bits;
         hipLaunchKernelGGL((k_seg_scatter<K, RB>), dim3(max_tiles), dim3(kBS), 0, st, ki, vi, ko,
                            vo, seg, tmp.tp, n_seg, shift, tmp.hist, last ? stride : 0u,
-                           last ? pay_src : nullptr, last ? pay_dst : nullptr, pay_stride);
+                           last ? pay_src : nullptr, last ? pay_dst : nullptr, pay_stride,
+                           last ? ranges : nullptr);
         cur ^= 1;
     }
     return cur;
@@ -761,8 +791,10 @@ uint64_t seg_sort_hist_entries(uint32_t n_max, int n_seg)
 int seg_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *seg,
                  int n_seg, uint32_t n_max, int bits, uint32_t seg_key_stride,
                  const SegSortTemp &tmp, hipStream_t st, const uint2 *pay_src, uint2 *pay_dst,
-                 uint32_t pay_stride)
+                 uint32_t pay_stride, uint2 *ranges)
 {
+    if (ranges && pay_dst)
+        throw std::invalid_argument("segmented sort: ranges are for key output, not a payload");
     if (bits <= 0) return 0;
     // as many 8-bit passes as needed, with the bits spread evenly over them
     // (narrower digits: fewer ballots per rank, longer runs per write)
@@ -770,7 +802,7 @@ int seg_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const u
     const int rb = (bits + passes - 1) / passes;
 #define GS_SEG(RB_)                                                                               \
     return seg_sort_rb<uint32_t, RB_>(k0, v0, k1, v1, seg, n_seg, n_max, bits, seg_key_stride,   \
-                                      pay_src, pay_dst, pay_stride, tmp, st);
+                                      pay_src, pay_dst, pay_stride, tmp, st, ranges);
     switch (rb) {
     case 1: case 2: case 3: case 4: GS_SEG(4)
     case 5: GS_SEG(5)

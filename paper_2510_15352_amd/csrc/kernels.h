@@ -155,12 +155,17 @@ void emit_instances(const uint32_t *dvals, const uint32_t *n_vis, uint32_t n_max
 // tile [0, seg[n_seg]) and seg[n_seg] <= n_max). The last pass adds
 // c * seg_key_stride to the keys of segment c; with pay_dst set it writes
 // pay_dst[i] = pay_src[value i * pay_stride] in sorted order instead of the
-// keys. Returns
+// keys. With ranges set (key output only), the last pass also folds every
+// output key's [first, last + 1) position into ranges[key] with atomic min
+// and max (the caller fills ranges with (~0, 0) first: fill_ranges). Returns
 // 0 if the result is in (k0, v0), 1 if in (k1, v1).
 int seg_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const uint32_t *seg,
                  int n_seg, uint32_t n_max, int bits, uint32_t seg_key_stride,
                  const SegSortTemp &tmp, hipStream_t st, const uint2 *pay_src = nullptr,
-                 uint2 *pay_dst = nullptr, uint32_t pay_stride = 1);
+                 uint2 *pay_dst = nullptr, uint32_t pay_stride = 1, uint2 *ranges = nullptr);
+// ranges[0 .. n) = (~0, 0): every tile's range empty until the tile sort
+// folds its instances in.
+void fill_ranges(uint2 *ranges, uint64_t n, hipStream_t st);
 uint64_t seg_sort_hist_entries(uint32_t n_max, int n_seg);
 
 // Calibration kernels (kind 0: FMA chains, 1: v_exp_f32 chains, 2: copy of
@@ -170,8 +175,6 @@ void launch_probe(int kind, float *scratch, int64_t n, int iters, const float4 *
 
 void launch_finalize_counts(uint32_t *counts, uint32_t cap, RenderFlags *flags, hipStream_t st);
 void launch_zero_u32(uint32_t *p, uint64_t n, hipStream_t st);
-void launch_ranges(const uint32_t *ikeys, const uint32_t *n_dev, uint2 *ranges, uint32_t n_max,
-                   hipStream_t st);
 bool raster_supported(int tw, int th, int b);
 int raster_occupancy(int tw, int th, int b);
 // count != nullptr selects the instrumented (pair-counting) grid kernel.

@@ -582,18 +582,17 @@ int enqueue_chunk_bins(gs_ctx *ctx, const Plan &P, const Chunk &c, Lane &L, hipS
     const uint64_t n_tiles = (uint64_t)c.count * P.tiles_per_cam;
     const int tbits = std::max(1, bits_for((uint64_t)P.tiles_per_cam));
     // radix passes inside each camera's segment, the last one turning
-    // the keys into camera * tiles + tile, then the ranges
+    // the keys into camera * tiles + tile and folding each tile's first and
+    // last instance into its range (every range empty before it)
+    t0 = T.begin();
+    fill_ranges(L.ranges.p, n_tiles, s);
+    T.end(GS_STAGE_RANGES, t0);
     t0 = T.begin();
     const int r2 = seg_sort_u32(L.ikeys[0].p, L.ivals[0].p, L.ikeys[1].p, L.ivals[1].p,
                                 L.inst_start.p, c.count, cap, tbits, (uint32_t)P.tiles_per_cam,
-                                sort, s);
+                                sort, s, nullptr, nullptr, 1, L.ranges.p);
     T.end(GS_STAGE_TILE_SORT, t0);
-    debug_check(ctx, s, "tile sort");
-    t0 = T.begin();
-    launch_zero_u32((uint32_t *)L.ranges.p, n_tiles * 2, s);
-    launch_ranges(L.ikeys[r2].p, L.counts.p + 2, L.ranges.p, cap, s);
-    T.end(GS_STAGE_RANGES, t0);
-    debug_check(ctx, s, "ranges");
+    debug_check(ctx, s, "tile sort and ranges");
     if (depth_half) *depth_half = r;
     return r2;
 }
