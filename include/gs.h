@@ -108,8 +108,8 @@ typedef struct {
 #define GS_STAGE_COMPACT 2 /* visibility scan + compaction */
 #define GS_STAGE_DEPTH_SORT 3
 #define GS_STAGE_EMIT 4    /* tile-count scan + instance emission */
-#define GS_STAGE_TILE_SORT 5
-#define GS_STAGE_RANGES 6
+#define GS_STAGE_TILE_SORT 5 /* tile sort; its last pass also writes the tile ranges */
+#define GS_STAGE_RANGES 6    /* emptying the tile ranges before the tile sort */
 #define GS_STAGE_RASTER 7
 #define GS_N_STAGES 8
 
