@@ -575,7 +575,8 @@ def main():
         args.steps = 100 if args.workload == 4 else 5
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(cameras shard across GPUs with no exchange; see the design notes)",
+              "(cameras shard across GPUs with no exchange between them, so one GPU's "
+              "share at its real shape is what this measures)",
               file=sys.stderr)
         sys.exit(2)
 
