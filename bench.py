@@ -531,6 +531,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--autotune-cache", default=None, metavar="PATH",
+                    help="autotune cache file (JSON lines): a result for this GPU and workload "
+                         "is read back instead of tuning, a new one appended")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (tile shape, LDS batch, chunk size, persistence) "
                          "and use the library's default choice")
@@ -605,10 +608,8 @@ def main():
         choice_kw = dict(tile=(tw, th), lds_batch=b, chunk_cams=c, persistent=args.form)
     if not args.no_autotune and not args.choice:
         t = time.time()
-        out_dir = os.path.join(ROOT, "gpurun_out")
         r.autotune(scene_ids, cams["poses"], cams["intrinsics"], W, H,
-                   cache_path=os.path.join(out_dir, "autotune.jsonl") if os.path.isdir(out_dir)
-                   else None)
+                   cache_path=args.autotune_cache)
         tuned = True
         log(f"autotune done in {time.time() - t:.1f}s")
 

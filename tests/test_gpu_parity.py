@@ -66,7 +66,7 @@ def test_projection_records_match_oracle(gpu_renderer, w0, w1, which):
     ref = oracle.project_all(sc, pose, intr, W, H)
     vis_ref = ref["visible"] > 0
     vis_got = got[:, 14] > 0
-    # the GPU machine is widened by rounding margins: it may keep a few extra
+    # the GPU's pixel box is widened by rounding margins: it may keep a few extra
     # Gaussians, never drop one the oracle sees
     assert np.all(vis_got[vis_ref]), np.nonzero(vis_ref & ~vis_got)[0][:10]
     assert (vis_got & ~vis_ref).sum() <= max(3, vis_ref.sum() // 1000)
@@ -81,7 +81,7 @@ def test_projection_records_match_oracle(gpu_renderer, w0, w1, which):
         assert err.max() < 1e-4, (name, err.max())
     for k, name in ((7, "r"), (8, "g"), (9, "b")):
         np.testing.assert_allclose(got[v, k], ref[name][v], atol=2e-5)
-    # GPU machine contains the oracle's exact box
+    # the GPU's pixel box contains the oracle's exact box
     assert np.all(got[v, 10] <= ref["x0"][v]) and np.all(got[v, 11] >= ref["x1"][v])
     assert np.all(got[v, 12] <= ref["y0"][v]) and np.all(got[v, 13] >= ref["y1"][v])
     # What the FP32 projection's errors do to alpha where the skip decision
@@ -572,7 +572,7 @@ def test_pair_and_visibility_counters_match_oracle(gpu_renderer, w0, w1):
     contributing (pixel, Gaussian) pairs equal up to the pixels with listed
     alternatives (each can differ by a few contributors); visible pairs and
     16x16-tile instances at least the oracle's exact-footprint counts (the
-    GPU machine is the exact box widened by a rounding margin) and at most a
+    GPU's pixel box is the exact box widened by a rounding margin) and at most a
     little above them."""
     for (sc, sid, cams), c, W, H in ((w0, 0, 64, 48), (w1, 5, 640, 480), (w1, 41, 640, 480)):
         gpu_renderer.render([sid], cams["poses"][c:c + 1], cams["intrinsics"][c:c + 1], W, H,
