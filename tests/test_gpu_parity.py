@@ -672,3 +672,51 @@ def test_extreme_gaussians_and_off_centre_principal_point(gpu_renderer):
             _check(ref, _np(rgb[k]), _np(depth[k]), _np(alpha[k]), f"extreme cam {k}")
     finally:
         gpu_renderer.release_scene(sid)
+
+
+def test_live_pixel_culls_on_partly_saturated_blocks(gpu_renderer):
+    """Stacks of three near-opaque splats in front saturate irregular patches
+    of pixels, so many 8x8 blocks go on with only part of their pixels live
+    while thousands of small splats behind still reach the rest. The walk
+    culls against the live pixels (their rectangle; on tiles of at most two
+    blocks also each record's box against the live lanes): every tile shape
+    must give the same frames bit for bit on a ragged 72x56 image, and the
+    oracle's. Every occluder sits at its own depth (no exact ties, which
+    other tests cover)."""
+    rng = np.random.default_rng(91)
+    sc = scenegen.tiny_scene(3000, 92, sh_degree=0, spread=0.8, log_scale_mean=-3.2)
+    occ = []
+    for k in range(7):
+        x, y = rng.uniform(-0.5, 0.5), rng.uniform(-0.4, 0.4)
+        for dz in (0.0, 0.05, 0.1):
+            occ.append(((x, y, 1.3 + 0.0137 * k + dz), (0.07, 0.05, 0.04), 0.97))
+    m = len(occ)
+    sc2 = dict(sh_degree=0)
+    sc2["means"] = np.concatenate([sc["means"], np.array([o[0] for o in occ])]).astype(np.float32)
+    sc2["scales"] = np.concatenate([sc["scales"], np.array([o[1] for o in occ])]).astype(np.float32)
+    sc2["quats"] = np.concatenate([sc["quats"], np.tile([1.0, 0.0, 0.0, 0.0], (m, 1))]).astype(np.float32)
+    sc2["opacity"] = np.concatenate([sc["opacity"], np.array([o[2] for o in occ])]).astype(np.float32)
+    sc2["sh"] = np.concatenate([sc["sh"], rng.normal(0, 0.5, size=(m, 1, 3))]).astype(np.float32)
+    sid = gpu_renderer.upload_scene(sc2)
+    try:
+        pose = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1).astype(np.float32)
+        poses = np.stack([pose, pose])
+        intr = np.array([[60.0, 60.0, 36.0, 28.0], [75.0, 70.0, 30.0, 25.0]], np.float32)
+        W, H = 72, 56
+        outs = {}
+        for tile, batch in (((16, 16), 64), ((16, 8), 64), ((8, 8), 64), ((32, 8), 128)):
+            outs[tile] = [_np(t) for t in gpu_renderer.render([sid] * 2, poses, intr, W, H,
+                                                             tile=tile, lds_batch=batch,
+                                                             persistent=0)]
+        base = outs[(16, 16)]
+        for tile, o in outs.items():
+            for x, y in zip(base, o):
+                assert np.array_equal(x, y), tile
+        for k in range(2):
+            stopped = float(np.mean(base[2][k] > 1.0 - 1e-3))
+            print(f"partly saturated cam {k}: stopped pixels {stopped:.2f}", flush=True)
+            assert 0.05 < stopped < 0.8
+            ref = oracle.render(sc2, poses[k], intr[k], W, H)
+            _check(ref, base[0][k], base[1][k], base[2][k], f"partly saturated cam {k}")
+    finally:
+        gpu_renderer.release_scene(sid)
