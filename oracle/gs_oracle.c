@@ -480,7 +480,8 @@ static int walk_plain(const cand_t *c, int n, const walk_cfg_t *cfg, double out[
  * tiles over the exact boxes, contributing pairs P, flagged pixels,
  * unresolved pixels (too many alternatives), candidate pairs, variants.
  * For flagged pixels the alternative results go to var_pix[k] (pixel index
- * y*W+x) and var_vals[k][5] = (r, g, b, depth, alpha) while k < var_cap;
+ * y*W+x) and var_vals[k][5] = (r, g, b, depth, alpha) while k < var_cap (an
+ * unresolved pixel gets one entry of NaNs: it has alternatives, none known);
  * *n_var receives the number of alternatives produced (may exceed var_cap).
  */
 int gso_render(const float *means, const float *scales, const float *quats,
@@ -610,7 +611,20 @@ int gso_render(const float *means, const float *scales, const float *quats,
                 }
                 if (!marginal && nr == 0 && !unres) { s = e; continue; }
                 ++n_flag;
-                if (unres || n_orders > MAX_ORDERS) { ++n_unres; s = e; continue; }
+                if (unres || n_orders > MAX_ORDERS) {
+                    /* no alternative can be listed: one entry of NaNs marks
+                     * the pixel as not plain, and matches nothing */
+                    ++n_unres;
+                    int64_t base;
+#pragma omp atomic capture
+                    { base = var_count; var_count += 1; }
+                    if (base < var_cap) {
+                        var_pix[base] = (int32_t)pix;
+                        for (int q = 0; q < 5; ++q) var_vals[base * 5 + q] = NAN;
+                    }
+                    s = e;
+                    continue;
+                }
                 if (cn > order_cap) {
                     order_cap = cn * 2;
                     order = (int *)realloc(order, sizeof(int) * order_cap);
